@@ -1,0 +1,176 @@
+/*
+ * ridge_detect.h -- C ABI of the MI355X (gfx950) ridge-directed circle Hough transform.
+ *
+ * The method (E. Afik, "Robust and highly performant ring detection algorithm for 3d
+ * particle tracking using 2d microscope imaging", Sci. Rep. 5, 13584):
+ *   1. Gaussian smoothing and 5x5 second-order Sobel derivatives; k_- = the smaller
+ *      Hessian eigenvalue and X_- its eigenvector (Methods, "Algorithm implementation";
+ *      SI, "Detailed algorithm", step 1).
+ *   2. Ridge pixels: k_- below a threshold that is <= 0 and a local minimum along X_-
+ *      (Results, "Directed ridge detection & votes collection"; SI step 2).
+ *   3. Each ridge pixel votes +1 for (x, y) +/- r X_- at every radius in
+ *      [r_min - 1, r_max + 1] (Results, same paragraph; SI, "Additional notes").
+ *   4. Accumulators exceeding an integer threshold are smoothed within their radius level
+ *      with Gaussian weights of width sigma(r) = slope r + intercept and divided by r; a
+ *      voxel is a ring if that score exceeds a fraction of 2 pi and it is the maximum of
+ *      its 3x3x3 box (Results, "Local maxima detection in a noisy parameter space";
+ *      Methods; SI step 4).
+ *   5. Ridge pixels inside an annulus around each peak are fitted by a circle for
+ *      sub-pixel (cx, cy, r) (Results, "Ridge points classification"; SI step 5).
+ *
+ * Conventions shared by every entry point:
+ *   - x = column, y = row, pixel centres at integers, (0, 0) at the top-left.
+ *   - No entry point throws; every one returns an rd_status.  Parameters and sizes are
+ *     validated on the host before any device work (RD_E_INVALID, RD_E_TOO_LARGE).
+ *   - "device pointer" arguments are HIP device memory owned by the caller; the work is
+ *     ordered on the stream given to rd_create and has completed when the call returns.
+ *   - Host arrays are owned by the caller.  The context owns all of its device scratch,
+ *     allocated in rd_create; no detection call allocates device memory.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef RIDGE_DETECT_H
+#define RIDGE_DETECT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RD_OK = 0,
+    RD_E_INVALID = 1,    /* bad parameter, null pointer, inconsistent sizes              */
+    RD_E_NOMEM = 2,      /* device or pinned-host allocation failed in rd_create          */
+    RD_E_DEVICE = 3,     /* no usable gfx950 device, or a HIP runtime error               */
+    RD_E_TOO_LARGE = 4,  /* frame or batch larger than the maxima given to rd_create       */
+    RD_E_TRUNCATED = 5,  /* output capacity too small; the count written is the required one */
+    RD_E_OVERFLOW = 6    /* an internal list (peaks) exceeded its capacity; result invalid */
+} rd_status;
+
+typedef enum { RD_U16 = 1, RD_F32 = 2 } rd_dtype;
+
+/* One image (Results, "Problem statement": an image containing rings).  Row-major,
+ * rows pitch_bytes apart.  u16 frames hold raw counts; f32 frames any real values. */
+typedef struct {
+    int32_t width;        /* >= 32 and <= rd_create_info.max_width                   */
+    int32_t height;       /* >= 32 and <= rd_create_info.max_height                  */
+    int64_t pitch_bytes;  /* >= width * element size                                 */
+    int32_t dtype;        /* rd_dtype                                                */
+    int32_t on_device;    /* 1: data is a device pointer; 0: host pointer (copied in) */
+    const void* data;
+} rd_frame;
+
+/* The method's knobs.  Limits checked by rd_validate_params are given per field. */
+typedef struct {
+    float sigma_smooth;       /* Gaussian scale-selection sigma, px; 0 < s <= 4 (Results,
+                                 scale selection at about the outer ring's scale)          */
+    float k_threshold;        /* curvature threshold T_k <= 0, image units / px^2 (SI step 2) */
+    int32_t r_min, r_max;     /* radius range, 1 <= r_min <= r_max <= 126, step 1 px       */
+    int32_t vote_threshold;   /* integer hotspot threshold: A > vote_threshold (SI step 4) */
+    float peak_fraction;      /* f: a peak needs S > f * 2 pi (SI step 4), 0 <= f          */
+    float sig_slope;          /* sigma(r) = sig_slope * r + sig_icpt (Methods: 0.05, 0.25) */
+    float sig_icpt;           /* slope >= 0, icpt > 0, ceil(3 sigma(r_max + 1)) <= 24      */
+    int32_t annulus_halfwidth;/* w: members satisfy (r-w)^2 <= d^2 <= (r+w)^2, 0 <= w <= 64 */
+    int32_t min_fit_points;   /* fewer annulus members than this: fit_ok = 0, >= 3         */
+} rd_params;
+
+/* One detected ring.  (a, b, r_bin) is the Hough peak voxel; (cx, cy, r) the circle fit
+ * (or the peak itself when fit_ok == 0); score = S at the peak (an ideal ring scores
+ * about 2 pi). */
+typedef struct {
+    float cx, cy, r, score;
+    int32_t a, b, r_bin;
+    int32_t n_fit;            /* annulus members used by the fit */
+    int32_t fit_ok;
+} rd_ring;
+
+typedef struct {
+    int32_t device;           /* HIP device ordinal                                        */
+    int32_t max_width;        /* largest frame the context accepts (<= 65535)              */
+    int32_t max_height;
+    int32_t max_peaks;        /* capacity of the per-frame peak list (> 0)                 */
+    int32_t max_frames;       /* largest batch for rd_detect_batch (>= 1)                  */
+    int64_t max_batch_pixels; /* sum of width*height over a batch (>= max_width*max_height) */
+    void* stream;             /* hipStream_t the context orders its work on; NULL = default */
+} rd_create_info;
+
+typedef struct rd_ctx* rd_handle;
+
+/* Human-readable name of a status code (static storage). */
+const char* rd_status_string(rd_status s);
+
+/* Host-only check of a parameter set; no device needed. */
+rd_status rd_validate_params(const rd_params* p);
+
+/* Host-only: the per-level tables the library derives from *p for radii r_min - 1 ..
+ * r_max + 1 (L = r_max - r_min + 3 levels; caller arrays of at least L entries, wtab of
+ * L * 25): ktab[i] = K(r) = ceil(3 sigma(r)), sigma(r) = sig_slope r + sig_icpt in double;
+ * wtab[i * 25 + d] = floor(2^15 exp(-d^2 / (2 sigma(r)^2)) + 1/2) for d <= K(r), else 0
+ * (the separable fixed-point smoothing factors, Methods "Algorithm implementation");
+ * thr[i] = floor(((f * 2 pi) * r) * 2^30), so that S > f 2 pi <=> S_int > thr (SI step 4).
+ * Any output may be NULL. */
+rd_status rd_level_tables(const rd_params* p, int32_t capacity_levels, int32_t* ktab, uint32_t* wtab,
+                          uint64_t* thr);
+
+/* Create a context on info->device; allocates all device scratch for the given maxima.
+ * *out is set to NULL on failure. */
+rd_status rd_create(const rd_create_info* info, rd_handle* out);
+
+/* Free a context and its device memory.  NULL is ignored. */
+void rd_destroy(rd_handle h);
+
+/* Full pipeline on one frame.  out is a host array of `capacity` rings; *n_rings receives
+ * the number of rings found, in ascending (r_bin, b, a) order.  If capacity is too small
+ * the first `capacity` rings are written, *n_rings holds the full count and the call
+ * returns RD_E_TRUNCATED. */
+rd_status rd_detect(rd_handle h, const rd_frame* frame, const rd_params* params,
+                    rd_ring* out, int32_t capacity, int32_t* n_rings);
+
+/* ---- kernel timing (measurement) ---------------------------------------------------- */
+
+/* Turn per-kernel timing on (1) or off (0).  When on, detection calls record HIP events on
+ * the context's stream around each kernel launch (a small per-launch cost). */
+rd_status rd_enable_timing(rd_handle h, int32_t enable);
+
+/* Accumulated kernel time since the last reset, per stage: [0] ridge kernel (steps 1-2),
+ * [1] vote/smooth/peak kernel (steps 3-4), [2] fit kernel (step 5); ms_total[i] in
+ * milliseconds and launches[i] the number of launches timed.  reset != 0 clears them. */
+rd_status rd_read_timing(rd_handle h, double* ms_total, int64_t* launches, int32_t reset);
+
+/* ---- stage entry points (parity checks; same kernels as rd_detect) ------------------- */
+
+/* Step 1 only: k_- (float, H x W, row-major, device pointer) and the direction code of
+ * X_- (int16 pairs (qx, qy) per pixel, H x W x 2, device pointer).  The code is
+ * rint(2^14 X_-) with qy > 0, or qy == 0 and qx > 0. */
+rd_status rd_stage_curvature(rd_handle h, const rd_frame* frame, const rd_params* params,
+                             float* k_dev, int16_t* q_dev);
+
+/* Steps 1-2: the ridge list (device pointers, each sized for `capacity` ridges):
+ * xy_dev = (x, y) int32 pairs, q_dev = (qx, qy) int16 pairs, k_dev = k_- as float; any of
+ * the three may be NULL.  The order is grouped by 16x16 pixel bin.  *n_ridges receives
+ * the count; RD_E_TRUNCATED if it exceeds capacity. */
+rd_status rd_stage_ridges(rd_handle h, const rd_frame* frame, const rd_params* params,
+                          int32_t* xy_dev, int16_t* q_dev, float* k_dev,
+                          int64_t capacity, int64_t* n_ridges);
+
+/* Step 3 (and the scores of step 4) from a caller-given ridge list: xy_dev = (x, y) int32
+ * pairs and q_dev = (qx, qy) int16 pairs for n ridges (device pointers; at most 256
+ * ridges per 16x16 bin, duplicates allowed within that).  acc_dev receives the dense vote
+ * accumulator, uint32 [L][height][width] with L = r_max - r_min + 3 levels for radii
+ * r_min - 1 .. r_max + 1.  score_dev (may be NULL) receives the integer smoothed score
+ * S_int = sum W(|dx|) W(|dy|) A (W = 15-bit fixed-point Gaussian factors) at hotspots and
+ * 0 elsewhere, uint64 [L][height][width]; the score is S = S_int / (r 2^30). */
+rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev,
+                              int64_t n, int32_t width, int32_t height,
+                              const rd_params* params, uint32_t* acc_dev, uint64_t* score_dev);
+
+/* Steps 3-5 from a caller-given ridge list (as rd_stage_accumulate); output as rd_detect. */
+rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev,
+                           int64_t n, int32_t width, int32_t height, const rd_params* params,
+                           rd_ring* out, int32_t capacity, int32_t* n_rings);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIDGE_DETECT_H */

@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP sources of the ridge-directed Hough library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ridge_detect.h"
+
+namespace rd {
+
+// Ridge pixels are stored per 16x16 pixel bin, in BIN_CAP slots per bin, so that the
+// vote and fit kernels can gather the ridges near any region without a global sort.
+constexpr int BIN = 16;
+constexpr int BIN_SHIFT = 4;
+constexpr int BIN_CAP = BIN * BIN;
+
+constexpr int RG_MAX = 16;   // Gaussian radius ceil(4 sigma) limit (sigma <= 4)
+constexpr int K_MAX = 24;    // smoothing window half-width limit
+constexpr int R_LIMIT = 126; // r_max limit: keeps u16 vote counts and u64 scores exact
+constexpr int MAX_DIM = 65535;
+
+// One frame of a launch: where its pixels are and where its tiles / bins start in the
+// launch-wide numbering.  A plain detection is a launch with one frame.
+struct FrameDesc {
+    const void* img;
+    int64_t pitch;       // bytes
+    int32_t W, H;
+    int32_t tile0;       // first stencil tile of this frame
+    int32_t vtile0;      // first vote tile of this frame
+    int64_t bin0;        // first ridge bin of this frame
+    int32_t nbx, nby;    // bins per row / column
+    int32_t peak0;       // first peak slot of this frame
+    int32_t pad;
+};
+
+struct Peak {
+    int32_t a, b, r, frame;
+    uint64_t s;          // integer smoothed score S_int
+};
+
+struct StencilArgs {
+    const FrameDesc* frames;
+    int32_t nframes;
+    int32_t total_tiles;
+    double g[RG_MAX + 1];    // g[0] centre tap, g[i] = g[-i]; zero beyond the radius
+    double k_threshold;
+    uint32_t* rxy;           // ridge (x | y << 16) per slot
+    uint32_t* rq;            // ridge (qx & 0xffff | qy << 16) per slot
+    float* rk;               // ridge k_- per slot
+    uint32_t* bin_count;     // ridges per bin
+    float* k_dense;          // dense outputs (stage mode, single frame)
+    int16_t* q_dense;
+};
+
+struct VoteArgs {
+    const FrameDesc* frames;
+    int32_t nframes;
+    int32_t total_vtiles;
+    int32_t nchunks;
+    const uint32_t* rxy;
+    const uint32_t* rq;
+    const uint32_t* bin_count;
+    int32_t lbase;            // r_min - 1: level index 0
+    int32_t vote_threshold;
+    const int32_t* chunk_start;  // [nchunks + 1] peak-level boundaries
+    const uint32_t* wtab;        // [level][K_MAX + 1] 15-bit weight factors
+    const int32_t* ktab;         // [level] window half-width
+    const uint64_t* thr;         // [level] integer score threshold
+    Peak* peaks;
+    uint32_t* peak_count;        // per frame
+    int32_t max_peaks;           // per frame
+    uint32_t* acc_dump;          // stage mode (single frame): dense [L][H][W]
+    uint64_t* score_dump;
+};
+
+struct FitArgs {
+    const FrameDesc* frames;
+    const uint32_t* rxy;
+    const uint32_t* bin_count;
+    const Peak* peaks;
+    const uint32_t* peak_count;  // per frame
+    int32_t nframes;
+    int32_t max_peaks;
+    int32_t w;
+    int32_t min_pts;
+    rd_ring* rings;              // [nframes * max_peaks], slot = frame peak0 + index
+};
+
+struct BinArgs {
+    const int32_t* xy;
+    const int16_t* q;
+    int64_t n;
+    int32_t W, H, nbx;
+    uint32_t* rxy;
+    uint32_t* rq;
+    float* rk;
+    uint32_t* bin_count;
+    uint32_t* overflow;
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, bool dense, hipStream_t s);
+int stencil_tile_w();
+int stencil_tile_h(int rg);
+
+constexpr int VOTE_TILE = 32;
+size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
+hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, hipStream_t s);
+hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s);
+hipError_t launch_bin(const BinArgs& a, hipStream_t s);
+hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* rk, const uint32_t* bin_count,
+                         const int64_t* offsets, int64_t nbins, int32_t* xy, int16_t* q, float* k, hipStream_t s);
+
+}  // namespace rd

@@ -1,0 +1,310 @@
+// Fused pre-processing + ridge kernel (method steps 1-2).
+//
+// One workgroup owns a TW x TH output tile of a frame and computes, entirely in LDS:
+//   load (reflect-101 borders, u16 or f32 -> f32)     input tile + (RG + 3) px halo
+//   horizontal Gaussian (fp64)                         rows of the input tile
+//   vertical Gaussian (fp64)                           smoothed image G on tile + 3 px
+//   5x5 second-order Sobel / 64 and the 2x2 eigensolve k_- (fp64) on tile + 1 px
+//   direction code q = rint(2^14 X_-) where k_- < T_k
+//   ridge test (k_- < T_k, strict minimum along the nearest lattice direction of X_-)
+//   and wave-ballot compaction of the ridge pixels into their 16x16 bins.
+// Only the input is read from HBM and only the ridges are written, so nothing of the
+// smoothed image, the Hessian or k_- ever goes to memory (except in the dense stage mode,
+// which writes k_- and q for parity checks).
+//
+// The filters run in fp64: the Hessian is a small difference of large smoothed values
+// (e.g. a 12-bit frame with a 600-count background and curvatures of order 1 count/px^2),
+// so fp32 would lose about 1e-4 absolute, far above the 1e-5 relative agreement the
+// results are held to.  CDNA fp64 FMA issues at the fp32 (non-packed) rate.
+//
+// Single reflect-101 extension of the raw image is enough for the two-step definition
+// (blur with mirrored borders, then Sobel with mirrored borders): with a symmetric
+// Gaussian the blurred extension is itself mirror-symmetric about both edges.
+#include "rd_internal.h"
+
+namespace rd {
+namespace {
+
+// Mirror about the edge pixel (-1 -> 1, n -> n-2).  Positions farther out than one
+// reflection only feed outputs outside the frame; they are clamped to stay in bounds.
+__device__ __forceinline__ int reflect101(int i, int n) {
+    i = i < 0 ? -i : i;
+    i = i > n - 1 ? 2 * (n - 1) - i : i;
+    return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+template <typename TIN>
+__device__ __forceinline__ float load_px(const void* img, int64_t pitch, int x, int y) {
+    const TIN* row = reinterpret_cast<const TIN*>(reinterpret_cast<const char*>(img) + (int64_t)y * pitch);
+    return static_cast<float>(row[x]);
+}
+
+// Direction code of X_- for the eigenvalue t - d of [[t+h, c], [c, t-h]], d = sqrt(h^2+c^2).
+// The eigenvector is (-c, h + d) for h >= 0 and (h - d, c) for h < 0 (no cancellation in
+// either branch); at an isotropic point (d == 0) X_- = (0, 1).
+__device__ __forceinline__ uint32_t direction_code(double h, double c, double d) {
+    double vx, vy;
+    if (d == 0.0) {
+        vx = 0.0;
+        vy = 1.0;
+    } else if (h >= 0.0) {
+        vx = -c;
+        vy = h + d;
+    } else {
+        vx = h - d;
+        vy = c;
+    }
+    const double inv = 16384.0 / sqrt(vx * vx + vy * vy);
+    int qx = static_cast<int>(rint(vx * inv));
+    int qy = static_cast<int>(rint(vy * inv));
+    if (qy < 0 || (qy == 0 && qx < 0)) {
+        qx = -qx;
+        qy = -qy;
+    }
+    return (static_cast<uint32_t>(qx) & 0xffffu) | (static_cast<uint32_t>(qy) << 16);
+}
+
+// Neighbour offset along X_-: nearest of the 8 lattice directions, in integers
+// (13573 / 32768 ~ tan(pi / 8)).
+__device__ __forceinline__ void nms_offset(uint32_t q, int& nx, int& ny) {
+    const int qx = static_cast<int16_t>(q & 0xffffu);
+    const int qy = static_cast<int16_t>(q >> 16);
+    const int ax = qx < 0 ? -qx : qx;
+    const int ay = qy < 0 ? -qy : qy;
+    if (13573 * ax > 32768 * ay) {
+        nx = 1; ny = 0;
+    } else if (13573 * ay > 32768 * ax) {
+        nx = 0; ny = 1;
+    } else {
+        nx = 1; ny = (qx * qy > 0) ? 1 : -1;
+    }
+}
+
+template <int TW_, int TH_, int RG_>
+struct StencilShape {
+    static constexpr int TW = TW_, TH = TH_, RG = RG_;
+    static constexpr int HALO = RG + 3;            // Gaussian + Sobel + NMS neighbour
+    static constexpr int IW = TW + 2 * HALO;       // input tile
+    static constexpr int IH = TH + 2 * HALO;
+    static constexpr int IWP = IW | 1;             // odd pitch: conflict-free row-per-lane reads
+    static constexpr int HC = TW + 6;              // columns of the horizontally smoothed rows
+    static constexpr int GH = TH + 6;              // rows of G
+    static constexpr int KW = TW + 2, KH = TH + 2; // k_- region (tile + 1 px)
+    static constexpr int MH = 10;                  // outputs per thread, horizontal pass
+    static constexpr int MV = 13;                  // vertical pass
+    static constexpr int MS = 12;                  // Sobel/eigen pass
+    static constexpr int NBX = TW / BIN, NBY = TH / BIN;
+    static constexpr int SZ_I = IH * IWP * 4;
+    static constexpr int SZ_G = GH * HC * 8;
+    static constexpr int SZ_H = IH * HC * 8;
+    static constexpr int SZ_K = KH * KW * 8;
+    static constexpr int SZ_Q = KH * KW * 4;
+    static constexpr int SZ_A = SZ_I > SZ_G ? SZ_I : SZ_G;
+    static constexpr int SZ_B = SZ_H > (SZ_K + SZ_Q) ? SZ_H : (SZ_K + SZ_Q);
+    static constexpr int LDS = SZ_A + SZ_B;
+    static_assert(TW % BIN == 0 && TH % BIN == 0, "tiles hold whole bins");
+    static_assert(LDS <= 65536, "static LDS limit");
+};
+
+constexpr int NT = 256;
+
+template <typename TIN, typename SH, bool DENSE>
+__global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
+    constexpr int TW = SH::TW, TH = SH::TH, RG = SH::RG, HALO = SH::HALO;
+    constexpr int IW = SH::IW, IH = SH::IH, IWP = SH::IWP, HC = SH::HC, GH = SH::GH;
+    constexpr int KW = SH::KW, KH = SH::KH, MH = SH::MH, MV = SH::MV, MS = SH::MS;
+    constexpr int NBX = SH::NBX, NB = SH::NBX * SH::NBY;
+
+    __shared__ __align__(16) uint8_t smem[SH::LDS];
+    __shared__ uint32_t wcount[NB][NT / 64];
+    float* sI = reinterpret_cast<float*>(smem);                 // region A
+    double* sG = reinterpret_cast<double*>(smem);               // region A (after sI dies)
+    double* sH = reinterpret_cast<double*>(smem + SH::SZ_A);    // region B
+    double* sK = reinterpret_cast<double*>(smem + SH::SZ_A);    // region B (after sH dies)
+    uint32_t* sQ = reinterpret_cast<uint32_t*>(smem + SH::SZ_A + SH::SZ_K);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const double kthr = a.k_threshold;
+
+    for (int t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
+        // ---- which frame / tile
+        int f = 0;
+        while (f + 1 < a.nframes && a.frames[f + 1].tile0 <= t) ++f;
+        const FrameDesc fd = a.frames[f];
+        const int W = fd.W, H = fd.H;
+        const int tiles_x = (W + TW - 1) / TW;
+        const int local = t - fd.tile0;
+        const int x0 = (local % tiles_x) * TW;
+        const int y0 = (local / tiles_x) * TH;
+
+        // ---- load the input tile with mirrored borders
+        for (int i = tid; i < IH * IW; i += NT) {
+            const int r = i / IW, c = i - r * IW;
+            const int gy = reflect101(y0 - HALO + r, H);
+            const int gx = reflect101(x0 - HALO + c, W);
+            sI[r * IWP + c] = load_px<TIN>(fd.img, fd.pitch, gx, gy);
+        }
+        __syncthreads();
+
+        // ---- horizontal Gaussian: sH[r][c] <- image x = x0 - 3 + c, all IH rows
+        constexpr int NSH = (HC + MH - 1) / MH;
+        for (int task = tid; task < IH * NSH; task += NT) {
+            const int r = task % IH, c0 = (task / IH) * MH;
+            const float* src = sI + r * IWP + c0;
+            double w[MH + 2 * RG];
+#pragma unroll
+            for (int i = 0; i < MH + 2 * RG; ++i) w[i] = (c0 + i < IW) ? static_cast<double>(src[i]) : 0.0;
+#pragma unroll
+            for (int m = 0; m < MH; ++m) {
+                double acc = a.g[0] * w[m + RG];
+#pragma unroll
+                for (int i = 1; i <= RG; ++i) acc = fma(a.g[i], w[m + RG - i] + w[m + RG + i], acc);
+                if (c0 + m < HC) sH[r * HC + c0 + m] = acc;
+            }
+        }
+        __syncthreads();
+
+        // ---- vertical Gaussian: sG[r][c] <- image (x0 - 3 + c, y0 - 3 + r)
+        constexpr int NSV = (GH + MV - 1) / MV;
+        for (int task = tid; task < HC * NSV; task += NT) {
+            const int c = task % HC, r0 = (task / HC) * MV;
+            double w[MV + 2 * RG];
+#pragma unroll
+            for (int i = 0; i < MV + 2 * RG; ++i) w[i] = (r0 + i < IH) ? sH[(r0 + i) * HC + c] : 0.0;
+#pragma unroll
+            for (int m = 0; m < MV; ++m) {
+                double acc = a.g[0] * w[m + RG];
+#pragma unroll
+                for (int i = 1; i <= RG; ++i) acc = fma(a.g[i], w[m + RG - i] + w[m + RG + i], acc);
+                if (r0 + m < GH) sG[(r0 + m) * HC + c] = acc;
+            }
+        }
+        __syncthreads();
+
+        // ---- Sobel / 64 and eigensolve: sK[r][c] <- image (x0 - 1 + c, y0 - 1 + r)
+        constexpr int NSS = (KH + MS - 1) / MS;
+        for (int task = tid; task < KW * NSS; task += NT) {
+            const int c = task % KW, r0 = (task / KW) * MS;
+            double d2x[MS + 4], s5x[MS + 4], d1x[MS + 4];
+#pragma unroll
+            for (int i = 0; i < MS + 4; ++i) {
+                const int gr = r0 + i < GH ? r0 + i : GH - 1;
+                const double* g = sG + gr * HC + c;
+                const double gm2 = g[0], gm1 = g[1], g0 = g[2], gp1 = g[3], gp2 = g[4];
+                d2x[i] = (gm2 + gp2) - 2.0 * g0;
+                s5x[i] = (gm2 + gp2) + 4.0 * (gm1 + gp1) + 6.0 * g0;
+                d1x[i] = (gp2 - gm2) + 2.0 * (gp1 - gm1);
+            }
+#pragma unroll
+            for (int m = 0; m < MS; ++m) {
+                const int r = r0 + m;
+                if (r < KH) {
+                    const double ixx = ((d2x[m] + d2x[m + 4]) + 4.0 * (d2x[m + 1] + d2x[m + 3]) + 6.0 * d2x[m + 2]) * (1.0 / 64.0);
+                    const double iyy = ((s5x[m] + s5x[m + 4]) - 2.0 * s5x[m + 2]) * (1.0 / 64.0);
+                    const double ixy = ((d1x[m + 4] - d1x[m]) + 2.0 * (d1x[m + 3] - d1x[m + 1])) * (1.0 / 64.0);
+                    const double tr = 0.5 * (ixx + iyy);
+                    const double h = 0.5 * (ixx - iyy);
+                    const double d = sqrt(h * h + ixy * ixy);
+                    const double k = tr - d;
+                    sK[r * KW + c] = k;
+                    sQ[r * KW + c] = (DENSE || k < kthr) ? direction_code(h, ixy, d) : 0u;
+                }
+            }
+        }
+        __syncthreads();
+
+        if (DENSE) {
+            // stage mode: k_- and q of the tile interior
+            for (int i = tid; i < TW * TH; i += NT) {
+                const int py = i / TW, px = i - py * TW;
+                const int x = x0 + px, y = y0 + py;
+                if (x < W && y < H) {
+                    const int o = (py + 1) * KW + px + 1;
+                    const int64_t g = (int64_t)y * W + x;
+                    a.k_dense[g] = static_cast<float>(sK[o]);
+                    const uint32_t q = sQ[o];
+                    a.q_dense[2 * g] = static_cast<int16_t>(q & 0xffffu);
+                    a.q_dense[2 * g + 1] = static_cast<int16_t>(q >> 16);
+                }
+            }
+        } else {
+            // ---- ridge test and compaction, one 16x16 bin per 256 threads
+            uint64_t masks[NB];
+            const int bpx = tid & (BIN - 1), bpy = tid >> BIN_SHIFT;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int px = (j % NBX) * BIN + bpx, py = (j / NBX) * BIN + bpy;
+                const int x = x0 + px, y = y0 + py;
+                bool ridge = false;
+                if (x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2) {
+                    const int o = (py + 1) * KW + px + 1;
+                    const double k = sK[o];
+                    if (k < kthr) {
+                        int nx, ny;
+                        nms_offset(sQ[o], nx, ny);
+                        ridge = (k < sK[o + ny * KW + nx]) && (k < sK[o - ny * KW - nx]);
+                    }
+                }
+                masks[j] = __ballot(ridge);
+                if (lane == 0) wcount[j][wave] = static_cast<uint32_t>(__popcll(masks[j]));
+            }
+            __syncthreads();
+            const int bx0 = x0 >> BIN_SHIFT, by0 = y0 >> BIN_SHIFT;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int bx = bx0 + (j % NBX), by = by0 + (j / NBX);
+                if (bx >= fd.nbx || by >= fd.nby) continue;
+                const int64_t bin = fd.bin0 + (int64_t)by * fd.nbx + bx;
+                const uint64_t m = masks[j];
+                if ((m >> lane) & 1ull) {
+                    uint32_t pos = static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+                    for (int w2 = 0; w2 < wave; ++w2) pos += wcount[j][w2];
+                    const int px = (j % NBX) * BIN + bpx, py = (j / NBX) * BIN + bpy;
+                    const int o = (py + 1) * KW + px + 1;
+                    const int64_t slot = bin * BIN_CAP + pos;
+                    a.rxy[slot] = static_cast<uint32_t>(x0 + px) | (static_cast<uint32_t>(y0 + py) << 16);
+                    a.rq[slot] = sQ[o];
+                    a.rk[slot] = static_cast<float>(sK[o]);
+                }
+                if (tid == 0) {
+                    uint32_t tot = 0;
+                    for (int w2 = 0; w2 < NT / 64; ++w2) tot += wcount[j][w2];
+                    a.bin_count[bin] = tot;
+                }
+            }
+        }
+        __syncthreads();   // LDS is reused by the next tile of a persistent block
+    }
+}
+
+template <typename TIN, int RG, bool DENSE>
+hipError_t launch_t(const StencilArgs& a, hipStream_t s) {
+    using SH = StencilShape<64, (RG <= 8 ? 32 : 16), RG>;
+    const int blocks = a.total_tiles;
+    hipLaunchKernelGGL((k_stencil<TIN, SH, DENSE>), dim3(blocks), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename TIN, bool DENSE>
+hipError_t launch_rg(const StencilArgs& a, int rg, hipStream_t s) {
+    if (rg <= 4) return launch_t<TIN, 4, DENSE>(a, s);
+    if (rg <= 8) return launch_t<TIN, 8, DENSE>(a, s);
+    if (rg <= 12) return launch_t<TIN, 12, DENSE>(a, s);
+    return launch_t<TIN, 16, DENSE>(a, s);
+}
+
+}  // namespace
+
+int stencil_tile_w() { return 64; }
+int stencil_tile_h(int rg) { return rg <= 8 ? 32 : 16; }
+
+hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, bool dense, hipStream_t s) {
+    if (dtype == RD_U16) {
+        return dense ? launch_rg<uint16_t, true>(a, rg, s) : launch_rg<uint16_t, false>(a, rg, s);
+    }
+    return dense ? launch_rg<float, true>(a, rg, s) : launch_rg<float, false>(a, rg, s);
+}
+
+}  // namespace rd
