@@ -15,8 +15,8 @@ namespace {
 
 constexpr double TWO_PI = 6.283185307179586;
 constexpr double S_SCALE = 1073741824.0;   // 2^30
-constexpr int CHUNK_MAX = 16;              // peak levels per vote workgroup
-constexpr size_t VOTE_LDS_BUDGET = 48 * 1024;
+constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per vote work item
+constexpr size_t VOTE_LDS_BUDGET = VOTE_LDS_MAX;
 
 #define RD_HIP(call)                                   \
     do {                                               \
@@ -211,6 +211,7 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.rq = h->d_rq;
     a.bin_count = h->d_bin_count;
     a.lbase = h->tabs.lbase;
+    a.nlevels = h->tabs.L;
     a.vote_threshold = p.vote_threshold;
     a.chunk_start = h->d_chunks;
     a.wtab = h->d_wtab;
@@ -219,6 +220,7 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.peaks = h->d_peaks;
     a.peak_count = h->d_counts;
     a.max_peaks = h->max_peaks;
+    a.error = h->d_counts + h->max_frames + 1;
     return a;
 }
 
@@ -272,6 +274,7 @@ rd_status vote_fit_collect(rd_ctx* h, const rd_params& p, FrameDesc& fd, rd_ring
     const int nvt = vote_tiles(fd.W, fd.H);
     fd.vtile0 = 0;
     RD_HIP(hipMemsetAsync(h->d_counts, 0, sizeof(uint32_t), h->stream));
+    RD_HIP(hipMemsetAsync(h->d_counts + h->max_frames + 1, 0, sizeof(uint32_t), h->stream));
     VoteArgs va = vote_args(h, p, 1, nvt);
     rd_status st = mark(h, 1);
     if (st != RD_OK) return st;
@@ -282,10 +285,12 @@ rd_status vote_fit_collect(rd_ctx* h, const rd_params& p, FrameDesc& fd, rd_ring
     RD_HIP(launch_fit(fa, 512, h->stream));
     st = mark(h, 3);
     if (st != RD_OK) return st;
-    RD_HIP(hipMemcpyAsync(h->h_counts, h->d_counts, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipMemcpyAsync(h->h_counts, h->d_counts, (h->max_frames + 2) * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     collect_timing(h, with_stencil);
     const uint32_t np = h->h_counts[0];
+    if (h->h_counts[h->max_frames + 1]) return RD_E_OVERFLOW;
     if (np > static_cast<uint32_t>(h->max_peaks)) {
         *n_rings = static_cast<int32_t>(np);
         return RD_E_OVERFLOW;
@@ -594,12 +599,15 @@ rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t*
     if (st != RD_OK) return st;
     const size_t vox = static_cast<size_t>(h->tabs.L) * width * height;
     if (score_dev) RD_HIP(hipMemsetAsync(score_dev, 0, vox * sizeof(uint64_t), h->stream));
-    RD_HIP(hipMemsetAsync(h->d_counts, 0, sizeof(uint32_t), h->stream));
+    RD_HIP(hipMemsetAsync(h->d_counts, 0, (h->max_frames + 2) * sizeof(uint32_t), h->stream));
     VoteArgs va = vote_args(h, *params, 1, vote_tiles(width, height));
     va.acc_dump = acc_dev;
     va.score_dump = score_dev;
     RD_HIP(launch_vote(va, h->tabs.lds, true, h->stream));
+    RD_HIP(hipMemcpyAsync(h->h_counts, h->d_counts, (h->max_frames + 2) * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
+    if (h->h_counts[h->max_frames + 1]) return RD_E_OVERFLOW;
     return RD_OK;
 }
 

@@ -58,19 +58,20 @@ __global__ __launch_bounds__(64) void k_fit(FitArgs a) {
             const int bxlo = max((pa - ro) >> BIN_SHIFT, 0), bxhi = min((pa + ro) >> BIN_SHIFT, fd.nbx - 1);
             const int bylo = max((pb - ro) >> BIN_SHIFT, 0), byhi = min((pb + ro) >> BIN_SHIFT, fd.nby - 1);
             int64_t n = 0, su = 0, sv = 0, suu = 0, suv = 0, svv = 0, sz = 0, suz = 0, svz = 0;
-            for (int by = bylo; by <= byhi; ++by) {
-                for (int bx = bxlo; bx <= bxhi; ++bx) {
-                    const int64_t bin = fd.bin0 + (int64_t)by * fd.nbx + bx;
-                    const uint32_t cnt = min(a.bin_count[bin], static_cast<uint32_t>(BIN_CAP));
-                    for (uint32_t i = lane; i < cnt; i += 64) {
-                        const uint32_t xy = a.rxy[bin * BIN_CAP + i];
-                        const int64_t u = static_cast<int>(xy & 0xffffu) - pa;
-                        const int64_t v = static_cast<int>(xy >> 16) - pb;
-                        const int64_t z = u * u + v * v;
-                        if (z >= ri2 && z <= ro2) {
-                            n += 1; su += u; sv += v; suu += u * u; suv += u * v; svv += v * v;
-                            sz += z; suz += u * z; svz += v * z;
-                        }
+            const int nbxr = bxhi - bxlo + 1;
+            const int nbin = nbxr * (byhi - bylo + 1);
+            for (int bi = lane; bi < nbin; bi += 64) {     // one bin per lane
+                const int by = bylo + bi / nbxr, bx = bxlo + bi % nbxr;
+                const int64_t bin = fd.bin0 + (int64_t)by * fd.nbx + bx;
+                const uint32_t cnt = min(a.bin_count[bin], static_cast<uint32_t>(BIN_CAP));
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    const uint32_t xy = a.rxy[bin * BIN_CAP + i];
+                    const int64_t u = static_cast<int>(xy & 0xffffu) - pa;
+                    const int64_t v = static_cast<int>(xy >> 16) - pb;
+                    const int64_t z = u * u + v * v;
+                    if (z >= ri2 && z <= ro2) {
+                        n += 1; su += u; sv += v; suu += u * u; suv += u * v; svv += v * v;
+                        sz += z; suz += u * z; svz += v * z;
                     }
                 }
             }

@@ -61,6 +61,7 @@ struct VoteArgs {
     const uint32_t* rq;
     const uint32_t* bin_count;
     int32_t lbase;            // r_min - 1: level index 0
+    int32_t nlevels;          // r_max - r_min + 3
     int32_t vote_threshold;
     const int32_t* chunk_start;  // [nchunks + 1] peak-level boundaries
     const uint32_t* wtab;        // [level][K_MAX + 1] 15-bit weight factors
@@ -69,6 +70,7 @@ struct VoteArgs {
     Peak* peaks;
     uint32_t* peak_count;        // per frame
     int32_t max_peaks;           // per frame
+    uint32_t* error;             // bit 0: a work item had more strong voxels than it holds
     uint32_t* acc_dump;          // stage mode (single frame): dense [L][H][W]
     uint64_t* score_dump;
 };
@@ -104,6 +106,8 @@ int stencil_tile_w();
 int stencil_tile_h(int rg);
 
 constexpr int VOTE_TILE = 32;
+constexpr int VOTE_LDS_MAX = 52 * 1024;   // dynamic LDS of the vote kernel (histogram)
+constexpr int VOTE_NLEV_MAX = 12;          // accumulator levels per level chunk
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, hipStream_t s);
 hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s);

@@ -25,7 +25,7 @@
 namespace rd {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 1024;
 constexpr int NW = NT / 64;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
@@ -57,24 +57,57 @@ __device__ __forceinline__ uint32_t get_u16(const uint32_t* s, int idx) {
     return (s[idx >> 1] >> ((idx & 1) << 4)) & 0xffffu;
 }
 
+constexpr int LMAX = R_LIMIT + 3;          // levels r_min - 1 .. r_max + 1 at most
+constexpr int NLEV_MAX = VOTE_NLEV_MAX;    // accumulator levels per level chunk
+constexpr int RCAP = 4096;                 // ridge records staged per tile
+constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the per-level fallback)
+constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
+
+// One block per CU walks the vote tiles of the launch.  For each tile it stages the ridge
+// records of every bin that can reach the tile at any radius in LDS once, then runs the
+// level chunks over them.
 template <int T, bool DUMP>
 __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
-    constexpr int SR = T + 2;
-    extern __shared__ __align__(16) uint32_t sA[];
-    __shared__ uint64_t sS[3 * SR * SR];
-    __shared__ uint16_t sHot[SR * SR];
-    __shared__ uint32_t sBin[NT];
-    __shared__ uint32_t sPre[NT + 1];
+    constexpr int SR = T + 2, SR2 = SR * SR;
+    static_assert(SR2 <= HCAP, "per-level fallback needs a whole score region in the list");
+    constexpr int BINS_PER_SIDE = ((T + 2 + 2 * K_MAX + 2 * (R_LIMIT + 2)) >> BIN_SHIFT) + 2;
+    static_assert(BINS_PER_SIDE * BINS_PER_SIDE <= NT, "one thread per candidate bin");
+    extern __shared__ __align__(16) uint32_t sA[];           // u16 histogram, two per word
+    __shared__ uint16_t sMap[NLEV_MAX * SR2];                // strong index + 1 per score voxel
+    __shared__ uint32_t sRidXY[RCAP];
+    __shared__ uint32_t sRidQ[RCAP];
+    __shared__ uint32_t sHot[HCAP];                          // (level << 16) | score-region index
+    __shared__ unsigned long long sHS[HCAP];                 // integer score per hotspot
+    __shared__ unsigned long long sStrongS[SCAP];
+    __shared__ uint32_t sStrongId[SCAP];
+    __shared__ uint32_t sBinPre[NT + 1];
+    __shared__ uint32_t sBinId[NT];
+    __shared__ uint16_t sWt[LMAX][K_MAX + 1];                // 15-bit weight factors
+    __shared__ unsigned long long sThr[LMAX];
+    __shared__ int32_t sKt[LMAX];
+    __shared__ int32_t sChunk[LMAX + 1];
     __shared__ uint32_t sWave[NW];
-    __shared__ uint32_t sCnt;
-    __shared__ uint32_t sWf[K_MAX + 1];
+    __shared__ uint32_t sNh, sNs;
 
     const int tid = threadIdx.x, lane = tid & 63;
-    const int n_items = a.total_vtiles * a.nchunks;
+    const int L = a.nlevels;
+    for (int i = tid; i < L * (K_MAX + 1); i += NT) {
+        const int li = i / (K_MAX + 1), d = i - li * (K_MAX + 1);
+        sWt[li][d] = static_cast<uint16_t>(a.wtab[i]);
+    }
+    for (int i = tid; i < L; i += NT) {
+        sThr[i] = a.thr[i];
+        sKt[i] = a.ktab[i];
+    }
+    for (int i = tid; i <= a.nchunks; i += NT) sChunk[i] = a.chunk_start[i];
+    for (int i = tid; i < (NLEV_MAX * SR2) / 2; i += NT) reinterpret_cast<uint32_t*>(sMap)[i] = 0u;
+    __syncthreads();
 
-    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int t = item / a.nchunks;
-        const int chunk = item - t * a.nchunks;
+    const int lbase = a.lbase;
+    const int r_lo = sChunk[0], r_hi = sChunk[a.nchunks];     // peak levels [r_lo, r_hi)
+    const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
+
+    for (int t = blockIdx.x; t < a.total_vtiles; t += gridDim.x) {
         int f = 0;
         while (f + 1 < a.nframes && a.frames[f + 1].vtile0 <= t) ++f;
         const FrameDesc fd = a.frames[f];
@@ -82,191 +115,293 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         const int tiles_x = (W + T - 1) / T;
         const int local = t - fd.vtile0;
         const int x0 = (local % tiles_x) * T, y0 = (local / tiles_x) * T;
-
-        const int rc0 = a.chunk_start[chunk], rc1 = a.chunk_start[chunk + 1];
-        const int l0 = rc0 - 1, l1 = rc1;           // accumulator levels, inclusive
-        const int Kc = a.ktab[l1 - a.lbase];        // widest window of the chunk
-        // score region (tile + 1 px) and accumulator region (+ K), clipped to the frame
         const int sx0 = max(x0 - 1, 0), sx1 = min(x0 + T + 1, W);
         const int sy0 = max(y0 - 1, 0), sy1 = min(y0 + T + 1, H);
-        const int ax0 = max(sx0 - Kc, 0), ax1 = min(sx1 + Kc, W);
-        const int ay0 = max(sy0 - Kc, 0), ay1 = min(sy1 + Kc, H);
-        const int AW = ax1 - ax0, AH = ay1 - ay0;
-        const int AWP = (AW + 1) & ~1;
-        const int plane = AWP * AH;                 // u16 per level, even
-        const int nlev = l1 - l0 + 1;
 
-        for (int i = tid; i < (nlev * plane) >> 1; i += NT) sA[i] = 0u;
-        __syncthreads();
-
-        // ---- gather the ridges of every bin that can reach the region, and vote
-        const int reach = l1 + 1;
-        const int bxlo = max((ax0 - reach) >> BIN_SHIFT, 0);
-        const int bxhi = min((ax1 - 1 + reach) >> BIN_SHIFT, fd.nbx - 1);
-        const int bylo = max((ay0 - reach) >> BIN_SHIFT, 0);
-        const int byhi = min((ay1 - 1 + reach) >> BIN_SHIFT, fd.nby - 1);
+        // ---- candidate bins: every bin whose pixels can vote into the tile's widest
+        // accumulator region at some radius of r_lo - 1 .. r_hi
+        const int Km = sKt[r_hi - lbase];
+        const int ux0 = max(sx0 - Km, 0), ux1 = min(sx1 + Km, W);
+        const int uy0 = max(sy0 - Km, 0), uy1 = min(sy1 + Km, H);
+        const int reach = r_hi + 1, far_lo = max(r_lo - 2, 0);
+        const int bxlo = max((ux0 - reach) >> BIN_SHIFT, 0), bxhi = min((ux1 - 1 + reach) >> BIN_SHIFT, fd.nbx - 1);
+        const int bylo = max((uy0 - reach) >> BIN_SHIFT, 0), byhi = min((uy1 - 1 + reach) >> BIN_SHIFT, fd.nby - 1);
         const int nbxr = bxhi - bxlo + 1;
         const int ncand = nbxr * (byhi - bylo + 1);
-        const int far_lo = max(l0 - 1, 0);
-        for (int cb = 0; cb < ncand; cb += NT) {
-            const int i = cb + tid;
-            uint32_t cnt = 0;
-            int64_t bin = 0;
-            if (i < ncand) {
-                const int bx = bxlo + i % nbxr, by = bylo + i / nbxr;
-                bin = fd.bin0 + (int64_t)by * fd.nbx + bx;
-                // pixel-box distances between the bin and the accumulator region
-                const int px0 = bx << BIN_SHIFT, px1 = px0 + BIN - 1;
-                const int py0 = by << BIN_SHIFT, py1 = py0 + BIN - 1;
-                const int gx = max(0, max(ax0 - px1, px0 - (ax1 - 1)));
-                const int gy = max(0, max(ay0 - py1, py0 - (ay1 - 1)));
-                const int fx = max(abs(px0 - (ax1 - 1)), abs(px1 - ax0));
-                const int fy = max(abs(py0 - (ay1 - 1)), abs(py1 - ay0));
-                const bool keep = gx * gx + gy * gy <= reach * reach && fx * fx + fy * fy >= far_lo * far_lo;
-                if (keep) cnt = min(a.bin_count[bin], static_cast<uint32_t>(BIN_CAP));
-            }
-            uint32_t total;
-            const uint32_t pre = block_excl_scan(cnt, sWave, &total);
-            sBin[tid] = static_cast<uint32_t>(bin - fd.bin0);
-            sPre[tid] = pre;
-            if (tid == 0) sPre[NT] = total;
-            __syncthreads();
-            for (uint32_t j = tid; j < total; j += NT) {
-                int lo = 0, hi = NT;            // largest lo with sPre[lo] <= j
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sPre[mid] <= j) lo = mid; else hi = mid;
-                }
-                const int64_t slot = (fd.bin0 + sBin[lo]) * BIN_CAP + (j - sPre[lo]);
-                const uint32_t xy = a.rxy[slot], q = a.rq[slot];
-                const int x = xy & 0xffffu, y = xy >> 16;
-                const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
-                for (int l = l0; l <= l1; ++l) {
-                    const int ox = (l * qx + 8192) >> 14, oy = (l * qy + 8192) >> 14;
-                    const int base = (l - l0) * plane;
-                    int u = x + ox - ax0, v = y + oy - ay0;
-                    if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) && static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
-                        const int idx = base + v * AWP + u;
-                        atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
-                    }
-                    u = x - ox - ax0;
-                    v = y - oy - ay0;
-                    if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) && static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
-                        const int idx = base + v * AWP + u;
-                        atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
-                    }
-                }
-            }
-            __syncthreads();
-        }
-
-        if (DUMP) {
-            const int ix1 = min(x0 + T, W), iy1 = min(y0 + T, H);
-            const int iw = ix1 - x0, ih = iy1 - y0;
-            for (int i = tid; i < nlev * iw * ih; i += NT) {
-                const int li = i / (iw * ih), rem = i - li * (iw * ih);
-                const int y = y0 + rem / iw, x = x0 + rem % iw;
-                a.acc_dump[((int64_t)(l0 + li - a.lbase) * H + y) * W + x] =
-                    get_u16(sA, li * plane + (y - ay0) * AWP + (x - ax0));
+        // at most (T + 2 + 2 K_MAX + 2 (R_LIMIT + 2)) / 16 + 2 = 23 bins per side (< NT in all)
+        uint32_t cnt = 0, bin_local = 0;
+        if (tid < ncand) {
+            const int by = bylo + tid / nbxr, bx = bxlo + (tid - (tid / nbxr) * nbxr);
+            const int px0 = bx << BIN_SHIFT, px1 = px0 + BIN - 1;
+            const int py0 = by << BIN_SHIFT, py1 = py0 + BIN - 1;
+            const int gx = max(0, max(ux0 - px1, px0 - (ux1 - 1)));
+            const int gy = max(0, max(uy0 - py1, py0 - (uy1 - 1)));
+            const int fx = max(abs(px0 - (ux1 - 1)), abs(px1 - ux0));
+            const int fy = max(abs(py0 - (uy1 - 1)), abs(py1 - uy0));
+            if (gx * gx + gy * gy <= reach * reach && fx * fx + fy * fy >= far_lo * far_lo) {
+                bin_local = static_cast<uint32_t>(by * fd.nbx + bx);
+                cnt = min(a.bin_count[fd.bin0 + bin_local], static_cast<uint32_t>(BIN_CAP));
             }
         }
+        uint32_t total;
+        const uint32_t pre = block_excl_scan(cnt, sWave, &total);
+        sBinPre[tid] = pre;
+        sBinId[tid] = bin_local;
+        if (tid == 0) sBinPre[NT] = total;
+        const int npieces = static_cast<int>((total + RCAP - 1) / RCAP);
+        __syncthreads();
 
-        // ---- per level: hotspot scores, threshold, and the 3x3x3 search one level behind
-        const int SW = sx1 - sx0, SHh = sy1 - sy0;
-        for (int l = l0; l <= l1; ++l) {
-            const int li = l - l0;
-            uint64_t* Sm = sS + (li % 3) * SR * SR;
-            const int lg = l - a.lbase;
-            for (int i = tid; i < SR * SR; i += NT) Sm[i] = 0ull;
-            if (tid == 0) sCnt = 0;
-            if (tid <= K_MAX) sWf[tid] = a.wtab[lg * (K_MAX + 1) + tid];
+        for (int c = 0; c < a.nchunks; ++c) {
+            const int rc0 = sChunk[c], rc1 = sChunk[c + 1];
+            const int l0 = rc0 - 1, l1 = rc1;                // accumulator levels, inclusive
+            const int nlev = l1 - l0 + 1;
+            const int Kc = sKt[l1 - lbase];                   // widest window of the chunk
+            const int ax0 = max(sx0 - Kc, 0), ax1 = min(sx1 + Kc, W);
+            const int ay0 = max(sy0 - Kc, 0), ay1 = min(sy1 + Kc, H);
+            const int AW = ax1 - ax0, AH = ay1 - ay0;
+            const int AWP = (AW + 7) & ~7;                    // 16-byte rows
+            const int plane = AWP * AH;                       // u16 per level, multiple of 8
+            {
+                const int words = (nlev * plane) >> 1;
+                uint4* a4 = reinterpret_cast<uint4*>(sA);
+                const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+                for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
+                for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
+            }
+            if (tid == 0) {
+                sNh = 0;
+                sNs = 0;
+            }
             __syncthreads();
-            const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
-            for (int i0 = 0; i0 < SW * SHh; i0 += NT) {
-                const int i = i0 + tid;
-                bool hot = false;
-                int sidx = 0;
-                if (i < SW * SHh) {
-                    const int vx = sx0 + i % SW, vy = sy0 + i / SW;
-                    hot = get_u16(sA, li * plane + (vy - ay0) * AWP + (vx - ax0)) > tint;
-                    sidx = (vy - (y0 - 1)) * SR + (vx - (x0 - 1));
+
+            // ---- votes of the staged ridges (staged once per tile unless they need pieces)
+            for (int pc = 0; pc < npieces; ++pc) {
+                const uint32_t pbase = static_cast<uint32_t>(pc) * RCAP;
+                const int pn = static_cast<int>(min(total - pbase, static_cast<uint32_t>(RCAP)));
+                if (npieces > 1 || c == 0) {
+                    for (int j = tid; j < pn; j += NT) {
+                        const uint32_t g = pbase + j;
+                        int lo = 0, hi = NT;                      // largest lo with sBinPre[lo] <= g
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (sBinPre[mid] <= g) lo = mid; else hi = mid;
+                        }
+                        const int64_t slot = (fd.bin0 + sBinId[lo]) * BIN_CAP + (g - sBinPre[lo]);
+                        sRidXY[j] = a.rxy[slot];
+                        sRidQ[j] = a.rq[slot];
+                    }
+                    __syncthreads();
                 }
-                const uint64_t m = __ballot(hot);
-                uint32_t base = 0;
-                if (lane == 0 && m) base = atomicAdd(&sCnt, static_cast<uint32_t>(__popcll(m)));
-                base = __shfl(base, 0, 64);
-                if (hot) sHot[base + __popcll(m & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(sidx);
-            }
-            __syncthreads();
-            const int nh = static_cast<int>(sCnt);
-            const int K = a.ktab[lg];
-            const uint32_t* wf = sWf;
-            const int rows = 2 * K + 1;
-            for (int task = tid; task < nh * rows; task += NT) {
-                const int h = task / rows, dy = task - h * rows - K;
-                const int sidx = sHot[h];
-                const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
-                const int yy = vy + dy;
-                if (yy < ay0 || yy >= ay1) continue;
-                const int xs = max(vx - K, ax0), xe = min(vx + K, ax1 - 1);
-                const int rowbase = li * plane + (yy - ay0) * AWP - ax0;
-                uint32_t rs = 0;
-                for (int x = xs; x <= xe; ++x) rs += wf[abs(x - vx)] * get_u16(sA, rowbase + x);
-                if (rs) atomicAdd(reinterpret_cast<unsigned long long*>(&Sm[sidx]),
-                                  static_cast<unsigned long long>(wf[abs(dy)]) * rs);
-            }
-            __syncthreads();
-            const uint64_t thr = a.thr[lg];
-            for (int h = tid; h < nh; h += NT) {
-                const int sidx = sHot[h];
-                const uint64_t s = Sm[sidx];
-                if (DUMP && a.score_dump) {
-                    const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
-                    if (vx >= x0 && vx < x0 + T && vy >= y0 && vy < y0 + T)
-                        a.score_dump[((int64_t)lg * H + vy) * W + vx] = s;
+                for (int j = tid; j < pn; j += NT) {
+                    const uint32_t xy = sRidXY[j], q = sRidQ[j];
+                    const int x = xy & 0xffffu, y = xy >> 16;
+                    const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
+#pragma unroll
+                    for (int s = 1; s >= -1; s -= 2) {
+                        const int sqx = s * qx, sqy = s * qy;
+                        // levels whose vote can fall in the region: |rho - l q / 2^14| <= 1/2 per axis
+                        float lo_l = static_cast<float>(l0), hi_l = static_cast<float>(l1);
+                        if (sqx != 0) {
+                            const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
+                            float e0 = (static_cast<float>(ax0 - x) - 0.5f) * inv;
+                            float e1 = (static_cast<float>(ax1 - 1 - x) + 0.5f) * inv;
+                            if (sqx < 0) { const float tt = e0; e0 = e1; e1 = tt; }
+                            lo_l = fmaxf(lo_l, e0);
+                            hi_l = fminf(hi_l, e1);
+                        } else if (x < ax0 || x >= ax1) {
+                            continue;
+                        }
+                        if (sqy != 0) {
+                            const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqy));
+                            float e0 = (static_cast<float>(ay0 - y) - 0.5f) * inv;
+                            float e1 = (static_cast<float>(ay1 - 1 - y) + 0.5f) * inv;
+                            if (sqy < 0) { const float tt = e0; e0 = e1; e1 = tt; }
+                            lo_l = fmaxf(lo_l, e0);
+                            hi_l = fminf(hi_l, e1);
+                        } else if (y < ay0 || y >= ay1) {
+                            continue;
+                        }
+                        if (!(lo_l <= hi_l + 2.0f)) continue;
+                        const int la = max(l0, static_cast<int>(floorf(lo_l)) - 1);
+                        const int lb = min(l1, static_cast<int>(ceilf(hi_l)) + 1);
+                        // fixed-point offsets, advanced by q per level; the mirrored vote is
+                        // x - rho(l, q), not x + rho(l, -q) (they differ at exact halves)
+                        int accx = la * qx + 8192, accy = la * qy + 8192;
+                        int base = (la - l0) * plane;
+                        for (int l = la; l <= lb; ++l) {
+                            const int u = x + s * (accx >> 14) - ax0;
+                            const int v = y + s * (accy >> 14) - ay0;
+                            if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) &&
+                                static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
+                                const int idx = base + v * AWP + u;
+                                atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
+                            }
+                            accx += qx;
+                            accy += qy;
+                            base += plane;
+                        }
+                    }
                 }
-                if (s <= thr) Sm[sidx] = 0ull;
+                __syncthreads();
             }
-            __syncthreads();
-            if (l - 1 >= rc0) {
-                const int lm = l - 1;
-                const uint64_t* Sp = sS + ((li + 1) % 3) * SR * SR;   // level l - 2
-                const uint64_t* Sc = sS + ((li + 2) % 3) * SR * SR;   // level l - 1
-                const uint64_t* Sn = Sm;                               // level l
-                for (int i = tid; i < T * T; i += NT) {
-                    const int iy = i / T, ix = i - iy * T;
-                    const int x = x0 + ix, y = y0 + iy;
-                    if (x >= W || y >= H) continue;
-                    const int o = (iy + 1) * SR + ix + 1;
-                    const uint64_t sv = Sc[o];
-                    if (!sv) continue;
-                    bool peak = true;
+
+            // ---- hotspots (A > T_int) of the score region: 16-byte loads (eight counters)
+            // over whole accumulator rows, flattened over (level, row, 16-byte column)
+            const int SHh = sy1 - sy0;
+            {
+                const int n8 = AWP >> 3;                          // 16-byte columns per row
+                const int rows = nlev * SHh;
+                const uint32_t units = static_cast<uint32_t>(rows * n8);
+                const uint32_t m8 = 0xffffffffu / static_cast<uint32_t>(n8) + 1u;    // x / n8 by mulhi
+                const uint32_t mS = 0xffffffffu / static_cast<uint32_t>(SHh) + 1u;
+                const uint4* a4 = reinterpret_cast<const uint4*>(sA);
+                for (uint32_t u = tid; u < units; u += NT) {
+                    const uint32_t rl = __umulhi(u, m8), c8 = u - rl * n8;
+                    const uint32_t li = __umulhi(rl, mS), r = rl - li * SHh;
+                    const int vy = sy0 + static_cast<int>(r);
+                    const uint4 w4 = a4[((li * plane + (vy - ay0) * AWP) >> 3) + c8];
+                    const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+                    uint32_t hotmask = 0;
 #pragma unroll
-                    for (int dl = -1; dl <= 1; ++dl) {
-                        const uint64_t* Sl = dl < 0 ? Sp : (dl == 0 ? Sc : Sn);
-                        const uint64_t ru = static_cast<uint64_t>(lm + dl);
-#pragma unroll
-                        for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-                            for (int dx = -1; dx <= 1; ++dx) {
-                                if (dl == 0 && dy == 0 && dx == 0) continue;
-                                const uint64_t su = Sl[o + dy * SR + dx];
-                                if (!su) continue;
-                                const uint64_t lhs = sv * ru, rhs = su * static_cast<uint64_t>(lm);
-                                const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                                if (earlier ? !(lhs > rhs) : !(lhs >= rhs)) peak = false;
+                    for (int k = 0; k < 4; ++k) {
+                        hotmask |= ((ws[k] & 0xffffu) > tint ? 1u : 0u) << (2 * k);
+                        hotmask |= ((ws[k] >> 16) > tint ? 1u : 0u) << (2 * k + 1);
+                    }
+                    while (hotmask) {
+                        const int k = __ffs(hotmask) - 1;
+                        hotmask &= hotmask - 1;
+                        const int vx = ax0 + static_cast<int>(c8) * 8 + k;
+                        if (vx >= sx0 && vx < sx1) {
+                            const uint32_t h = atomicAdd(&sNh, 1u);
+                            if (h < static_cast<uint32_t>(HCAP)) {
+                                sHot[h] = (li << 16) | static_cast<uint32_t>((vy - (y0 - 1)) * SR + (vx - (x0 - 1)));
+                                sHS[h] = 0ull;
                             }
                         }
                     }
-                    if (peak) {
-                        const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
-                        if (idx < static_cast<uint32_t>(a.max_peaks)) {
-                            Peak pk;
-                            pk.a = x; pk.b = y; pk.r = lm; pk.frame = f; pk.s = sv;
-                            a.peaks[fd.peak0 + idx] = pk;
+                }
+            }
+            __syncthreads();
+
+            if (DUMP) {
+                const int ix1 = min(x0 + T, W), iy1 = min(y0 + T, H);
+                const int iw = ix1 - x0, ih = iy1 - y0;
+                for (int li = 0; li < nlev; ++li)
+                    for (int i = tid; i < iw * ih; i += NT) {
+                        const int y = y0 + i / iw, x = x0 + i % iw;
+                        a.acc_dump[((int64_t)(l0 + li - lbase) * H + y) * W + x] =
+                            get_u16(sA, li * plane + (y - ay0) * AWP + (x - ax0));
+                    }
+            }
+
+            // ---- integer scores of the hotspots, then the strong (above-threshold) ones
+            const uint32_t nh_all = sNh;
+            const bool per_level = nh_all > static_cast<uint32_t>(HCAP);
+            const int rowsmax = 2 * Kc + 1;
+            const int npass = per_level ? nlev : 1;
+            for (int pass = 0; pass < npass; ++pass) {
+                if (per_level) {
+                    // rare: more hotspots than the list holds; enumerate one level at a time
+                    __syncthreads();
+                    if (tid == 0) sNh = 0;
+                    __syncthreads();
+                    const int SW = sx1 - sx0;
+                    for (int i = tid; i < SW * SHh; i += NT) {
+                        const int vy = sy0 + i / SW, vx = sx0 + i % SW;
+                        if (get_u16(sA, pass * plane + (vy - ay0) * AWP + (vx - ax0)) > tint) {
+                            const uint32_t h = atomicAdd(&sNh, 1u);
+                            sHot[h] = (static_cast<uint32_t>(pass) << 16) |
+                                      static_cast<uint32_t>((vy - (y0 - 1)) * SR + (vx - (x0 - 1)));
+                            sHS[h] = 0ull;
+                        }
+                    }
+                    __syncthreads();
+                }
+                const int nh = static_cast<int>(min(sNh, static_cast<uint32_t>(HCAP)));
+                for (int task = tid; task < nh * rowsmax; task += NT) {
+                    const int h = task / rowsmax;
+                    const int dy = task - h * rowsmax - Kc;
+                    const uint32_t e = sHot[h];
+                    const int li = e >> 16, sidx = e & 0xffff;
+                    const int lg = l0 + li - lbase;
+                    const int K = sKt[lg];
+                    if (dy < -K || dy > K) continue;
+                    const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
+                    const int yy = vy + dy;
+                    if (yy < ay0 || yy >= ay1) continue;
+                    const int xs = max(vx - K, ax0), xe = min(vx + K, ax1 - 1);
+                    const int rowbase = li * plane + (yy - ay0) * AWP - ax0;
+                    const uint16_t* wf = sWt[lg];
+                    uint32_t rs = 0;
+                    for (int x = xs; x <= xe; ++x) rs += static_cast<uint32_t>(wf[abs(x - vx)]) * get_u16(sA, rowbase + x);
+                    if (rs) atomicAdd(&sHS[h], static_cast<unsigned long long>(wf[dy < 0 ? -dy : dy]) * rs);
+                }
+                __syncthreads();
+                for (int h = tid; h < nh; h += NT) {
+                    const uint32_t e = sHot[h];
+                    const int li = e >> 16, sidx = e & 0xffff;
+                    const unsigned long long sc = sHS[h];
+                    if (DUMP && a.score_dump) {
+                        const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
+                        if (vx >= x0 && vx < x0 + T && vy >= y0 && vy < y0 + T)
+                            a.score_dump[((int64_t)(l0 + li - lbase) * H + vy) * W + vx] = sc;
+                    }
+                    if (sc > sThr[l0 + li - lbase]) {
+                        const uint32_t j = atomicAdd(&sNs, 1u);
+                        if (j < static_cast<uint32_t>(SCAP)) {
+                            sStrongS[j] = sc;
+                            sStrongId[j] = e;
+                            sMap[li * SR2 + sidx] = static_cast<uint16_t>(j + 1);
+                        } else {
+                            atomicOr(a.error, 1u);
                         }
                     }
                 }
+            }
+            __syncthreads();
+
+            // ---- 3x3x3 comparison of the strong voxels of the peak levels [rc0, rc1)
+            const int ns = static_cast<int>(min(sNs, static_cast<uint32_t>(SCAP)));
+            for (int j = tid; j < ns; j += NT) {
+                const uint32_t e = sStrongId[j];
+                const int li = e >> 16, sidx = e & 0xffff;
+                const int lm = l0 + li;
+                if (lm < rc0 || lm >= rc1) continue;
+                const int sxr = sidx % SR, syr = sidx / SR;
+                if (sxr < 1 || sxr > T || syr < 1 || syr > T) continue;
+                const int vx = x0 - 1 + sxr, vy = y0 - 1 + syr;
+                if (vx >= W || vy >= H) continue;
+                uint16_t nb[27];
+#pragma unroll
+                for (int k = 0; k < 27; ++k) {
+                    const int dl = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+                    nb[k] = sMap[(li + dl) * SR2 + sidx + dy * SR + dx];
+                }
+                const unsigned long long sv = sStrongS[j];
+                bool peak = true;
+#pragma unroll
+                for (int k = 0; k < 27; ++k) {
+                    if (k == 13 || !nb[k]) continue;
+                    const int dl = k / 9 - 1;
+                    const unsigned long long su = sStrongS[nb[k] - 1];
+                    const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
+                    const unsigned long long rhs = su * static_cast<unsigned long long>(lm);
+                    // neighbours before v in (r, y, x) order are the first 13 of the box
+                    if (k < 13 ? !(lhs > rhs) : !(lhs >= rhs)) peak = false;
+                }
+                if (peak) {
+                    const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
+                    if (idx < static_cast<uint32_t>(a.max_peaks)) {
+                        Peak pk;
+                        pk.a = vx; pk.b = vy; pk.r = lm; pk.frame = f; pk.s = sv;
+                        a.peaks[fd.peak0 + idx] = pk;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int j = tid; j < ns; j += NT) {          // leave the map clean for the next chunk
+                const uint32_t e = sStrongId[j];
+                sMap[(e >> 16) * SR2 + (e & 0xffff)] = 0;
             }
             __syncthreads();
         }
@@ -329,32 +464,36 @@ hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* r
 
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax) {
     const int side = tile + 2 + 2 * kmax;
-    const size_t plane = (size_t)((side + 1) & ~1) * side;
+    const size_t plane = (size_t)((side + 7) & ~7) * side;
     return ((nlev_max * plane * 2 + 15) / 16) * 16;
 }
 
 static bool g_attr_set[2] = {false, false};
+static int g_cus = 0;
 
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, hipStream_t s) {
-    const int items = a.total_vtiles * a.nchunks;
-    if (items <= 0) return hipSuccess;
-    if (dump) {
-        if (!g_attr_set[1]) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, true>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-            if (e != hipSuccess) return e;
-            g_attr_set[1] = true;
-        }
-        hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(items), dim3(NT), lds, s, a);
-    } else {
-        if (!g_attr_set[0]) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-            if (e != hipSuccess) return e;
-            g_attr_set[0] = true;
-        }
-        hipLaunchKernelGGL((k_vote<VOTE_TILE, false>), dim3(items), dim3(NT), lds, s, a);
+    const int items = a.total_vtiles;
+    if (items <= 0 || a.nchunks <= 0) return hipSuccess;
+    if (!g_cus) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
     }
+    const int blocks = items < g_cus ? items : g_cus;   // persistent: one block per CU, a tile per step
+    const void* fn = dump ? reinterpret_cast<const void*>(&k_vote<VOTE_TILE, true>)
+                          : reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false>);
+    bool& set = g_attr_set[dump ? 1 : 0];
+    if (!set) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
+        if (e != hipSuccess) return e;
+        set = true;
+    }
+    if (dump)
+        hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(blocks), dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_vote<VOTE_TILE, false>), dim3(blocks), dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 
