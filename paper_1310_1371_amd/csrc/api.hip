@@ -221,6 +221,7 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.peak_count = h->d_counts;
     a.max_peaks = h->max_peaks;
     a.error = h->d_counts + h->max_frames + 1;
+    a.tile_counter = h->d_counts + h->max_frames + 2;
     return a;
 }
 
@@ -274,7 +275,7 @@ rd_status vote_fit_collect(rd_ctx* h, const rd_params& p, FrameDesc& fd, rd_ring
     const int nvt = vote_tiles(fd.W, fd.H);
     fd.vtile0 = 0;
     RD_HIP(hipMemsetAsync(h->d_counts, 0, sizeof(uint32_t), h->stream));
-    RD_HIP(hipMemsetAsync(h->d_counts + h->max_frames + 1, 0, sizeof(uint32_t), h->stream));
+    RD_HIP(hipMemsetAsync(h->d_counts + h->max_frames + 1, 0, 2 * sizeof(uint32_t), h->stream));
     VoteArgs va = vote_args(h, p, 1, nvt);
     rd_status st = mark(h, 1);
     if (st != RD_OK) return st;
@@ -440,7 +441,7 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_rk), slots * 4) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_bin_count), h->max_bins * 4) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_peaks), npk * sizeof(Peak)) == hipSuccess;
-    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_counts), (h->max_frames + 2) * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_counts), (h->max_frames + 4) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_rings), npk * sizeof(rd_ring)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_frames), h->max_frames * sizeof(FrameDesc)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_wtab), (R_LIMIT + 3) * (K_MAX + 1) * sizeof(uint32_t)) == hipSuccess;
@@ -449,7 +450,7 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_chunks), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_offsets), bins_single * sizeof(int64_t)) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_rings), npk * sizeof(rd_ring)) == hipSuccess;
-    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 2) * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_frames), h->max_frames * sizeof(FrameDesc)) == hipSuccess;
     if (!ok) {
         rd_destroy(h);
@@ -599,7 +600,7 @@ rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t*
     if (st != RD_OK) return st;
     const size_t vox = static_cast<size_t>(h->tabs.L) * width * height;
     if (score_dev) RD_HIP(hipMemsetAsync(score_dev, 0, vox * sizeof(uint64_t), h->stream));
-    RD_HIP(hipMemsetAsync(h->d_counts, 0, (h->max_frames + 2) * sizeof(uint32_t), h->stream));
+    RD_HIP(hipMemsetAsync(h->d_counts, 0, (h->max_frames + 4) * sizeof(uint32_t), h->stream));
     VoteArgs va = vote_args(h, *params, 1, vote_tiles(width, height));
     va.acc_dump = acc_dev;
     va.score_dump = score_dev;

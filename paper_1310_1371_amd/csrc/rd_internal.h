@@ -71,6 +71,7 @@ struct VoteArgs {
     uint32_t* peak_count;        // per frame
     int32_t max_peaks;           // per frame
     uint32_t* error;             // bit 0: a work item had more strong voxels than it holds
+    uint32_t* tile_counter;      // work queue of vote tiles (zero before the launch)
     uint32_t* acc_dump;          // stage mode (single frame): dense [L][H][W]
     uint64_t* score_dump;
 };
@@ -106,7 +107,7 @@ int stencil_tile_w();
 int stencil_tile_h(int rg);
 
 constexpr int VOTE_TILE = 32;
-constexpr int VOTE_LDS_MAX = 52 * 1024;   // dynamic LDS of the vote kernel (histogram)
+constexpr int VOTE_LDS_MAX = 56 * 1024;   // with ~101 KB of static LDS: ~157 KB of 160   // dynamic LDS of the vote kernel (histogram)
 constexpr int VOTE_NLEV_MAX = 12;          // accumulator levels per level chunk
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, hipStream_t s);

@@ -62,6 +62,16 @@ constexpr int NLEV_MAX = VOTE_NLEV_MAX;    // accumulator levels per level chunk
 constexpr int RCAP = 4096;                 // ridge records staged per tile
 constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the per-level fallback)
 constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
+constexpr int WB = K_MAX + 1;              // centre of the padded weight row
+constexpr int DCAP = HCAP * 3;             // sorted vote runs per pass (in the hotspot bytes)
+constexpr int PPT = RCAP / NT;             // staged ridges per thread
+
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+
+// sum of two u16 x u16 products, accumulated in u32 (v_dot2_u32_u16)
+__device__ __forceinline__ uint32_t dot2_u16(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_udot2(__builtin_bit_cast(ushort2_t, a), __builtin_bit_cast(ushort2_t, b), c, false);
+}
 
 // One block per CU walks the vote tiles of the launch.  For each tile it stages the ridge
 // records of every bin that can reach the tile at any radius in LDS once, then runs the
@@ -76,13 +86,22 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ uint16_t sMap[NLEV_MAX * SR2];                // strong index + 1 per score voxel
     __shared__ uint32_t sRidXY[RCAP];
     __shared__ uint32_t sRidQ[RCAP];
-    __shared__ uint32_t sHot[HCAP];                          // (level << 16) | score-region index
-    __shared__ unsigned long long sHS[HCAP];                 // integer score per hotspot
+    // hotspot list and scores; while voting, the same bytes hold the vote runs
+    __shared__ __align__(16) uint8_t sScratch[HCAP * 12];
+    uint32_t* const sHot = reinterpret_cast<uint32_t*>(sScratch);                        // (level << 16) | index
+    unsigned long long* const sHS = reinterpret_cast<unsigned long long*>(sScratch + HCAP * 4);
+    uint32_t* const sDesc = reinterpret_cast<uint32_t*>(sScratch);                       // runs sorted by length
+    __shared__ uint32_t sBk[NLEV_MAX + 2];                   // runs per length, then offsets
     __shared__ unsigned long long sStrongS[SCAP];
     __shared__ uint32_t sStrongId[SCAP];
     __shared__ uint32_t sBinPre[NT + 1];
     __shared__ uint32_t sBinId[NT];
     __shared__ uint16_t sWt[LMAX][K_MAX + 1];                // 15-bit weight factors
+    // per chunk level: weights W(|o - WB|) for o = 0 .. 2 WB + 1 (zero beyond K), as u16 pairs
+    // starting at even (sWpE) and odd (sWpO) o, for two-tap dot products
+    __shared__ uint32_t sWpE[NLEV_MAX][WB + 1];
+    __shared__ uint32_t sWpO[NLEV_MAX][WB + 1];
+    __shared__ int sTile;
     __shared__ unsigned long long sThr[LMAX];
     __shared__ int32_t sKt[LMAX];
     __shared__ int32_t sChunk[LMAX + 1];
@@ -107,7 +126,12 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     const int r_lo = sChunk[0], r_hi = sChunk[a.nchunks];     // peak levels [r_lo, r_hi)
     const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
 
-    for (int t = blockIdx.x; t < a.total_vtiles; t += gridDim.x) {
+    for (;;) {
+        // tiles are taken from a queue: their cost varies with the number of hotspots
+        if (tid == 0) sTile = static_cast<int>(atomicAdd(a.tile_counter, 1u));
+        __syncthreads();
+        const int t = sTile;
+        if (t >= a.total_vtiles) break;
         int f = 0;
         while (f + 1 < a.nframes && a.frames[f + 1].vtile0 <= t) ++f;
         const FrameDesc fd = a.frames[f];
@@ -159,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             const int ax0 = max(sx0 - Kc, 0), ax1 = min(sx1 + Kc, W);
             const int ay0 = max(sy0 - Kc, 0), ay1 = min(sy1 + Kc, H);
             const int AW = ax1 - ax0, AH = ay1 - ay0;
-            const int AWP = (AW + 7) & ~7;                    // 16-byte rows
+            const int AWP = (AW + 8) & ~7;                    // 16-byte rows, >= 1 zero column
             const int plane = AWP * AH;                       // u16 per level, multiple of 8
             {
                 const int words = (nlev * plane) >> 1;
@@ -167,6 +191,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 const uint4 z = make_uint4(0u, 0u, 0u, 0u);
                 for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
                 for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
+            }
+            for (int i = tid; i < nlev * (WB + 1); i += NT) {
+                const int li = i / (WB + 1), j = i - li * (WB + 1);
+                const int lg = l0 + li - lbase, K = sKt[lg];
+                uint32_t wl[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int o = 2 * j + k, d = o > WB ? o - WB : WB - o;
+                    wl[k] = (o <= 2 * WB + 1 && d <= K) ? static_cast<uint32_t>(sWt[lg][d]) : 0u;
+                }
+                sWpE[li][j] = wl[0] | (wl[1] << 16);
+                sWpO[li][j] = wl[1] | (wl[2] << 16);
             }
             if (tid == 0) {
                 sNh = 0;
@@ -192,15 +228,35 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     }
                     __syncthreads();
                 }
-                for (int j = tid; j < pn; j += NT) {
-                    const uint32_t xy = sRidXY[j], q = sRidQ[j];
+                // vote runs: for each staged ridge and sign, the levels whose vote can fall in
+                // this chunk's region.  The runs are bucketed by length (a counting sort in LDS)
+                // so that a wave works on runs of equal length.
+                if (tid < NLEV_MAX + 2) sBk[tid] = 0u;
+                __syncthreads();
+                uint32_t run[2 * PPT];                         // (la - l0) | length << 8
+                const int dlo = max(l0 - 1, 0), dhi = l1 + 1;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    run[2 * k] = 0u;
+                    run[2 * k + 1] = 0u;
+                    const int j = k * NT + tid;
+                    if (j >= pn) continue;
+                    const uint32_t xy = sRidXY[j];
                     const int x = xy & 0xffffu, y = xy >> 16;
+                    // |vote - p| is within 0.72 px of the level: distance screen first
+                    const int gx = max(0, max(ax0 - x, x - (ax1 - 1)));
+                    const int gy = max(0, max(ay0 - y, y - (ay1 - 1)));
+                    const int fx = max(abs(x - ax0), abs(x - (ax1 - 1)));
+                    const int fy = max(abs(y - ay0), abs(y - (ay1 - 1)));
+                    if (gx * gx + gy * gy > dhi * dhi || fx * fx + fy * fy < dlo * dlo) continue;
+                    const uint32_t q = sRidQ[j];
                     const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
 #pragma unroll
-                    for (int s = 1; s >= -1; s -= 2) {
-                        const int sqx = s * qx, sqy = s * qy;
-                        // levels whose vote can fall in the region: |rho - l q / 2^14| <= 1/2 per axis
+                    for (int sg = 0; sg < 2; ++sg) {
+                        const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
+                        // |rho - l q / 2^14| <= 1/2 per axis bounds the levels that can land
                         float lo_l = static_cast<float>(l0), hi_l = static_cast<float>(l1);
+                        bool ok = true;
                         if (sqx != 0) {
                             const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
                             float e0 = (static_cast<float>(ax0 - x) - 0.5f) * inv;
@@ -208,8 +264,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             if (sqx < 0) { const float tt = e0; e0 = e1; e1 = tt; }
                             lo_l = fmaxf(lo_l, e0);
                             hi_l = fminf(hi_l, e1);
-                        } else if (x < ax0 || x >= ax1) {
-                            continue;
+                        } else {
+                            ok = x >= ax0 && x < ax1;
                         }
                         if (sqy != 0) {
                             const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqy));
@@ -218,17 +274,49 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             if (sqy < 0) { const float tt = e0; e0 = e1; e1 = tt; }
                             lo_l = fmaxf(lo_l, e0);
                             hi_l = fminf(hi_l, e1);
-                        } else if (y < ay0 || y >= ay1) {
-                            continue;
+                        } else {
+                            ok = ok && y >= ay0 && y < ay1;
                         }
-                        if (!(lo_l <= hi_l + 2.0f)) continue;
+                        if (!ok || !(lo_l <= hi_l + 2.0f)) continue;
                         const int la = max(l0, static_cast<int>(floorf(lo_l)) - 1);
                         const int lb = min(l1, static_cast<int>(ceilf(hi_l)) + 1);
-                        // fixed-point offsets, advanced by q per level; the mirrored vote is
-                        // x - rho(l, q), not x + rho(l, -q) (they differ at exact halves)
+                        if (lb < la) continue;
+                        const int len = lb - la + 1;           // 1 .. nlev <= NLEV_MAX
+                        run[2 * k + sg] = static_cast<uint32_t>(la - l0) | (static_cast<uint32_t>(len) << 8);
+                        atomicAdd(&sBk[len], 1u);
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    uint32_t acc = 0;
+                    for (int len = 1; len <= NLEV_MAX; ++len) {
+                        const uint32_t c = sBk[len];
+                        sBk[len] = acc;
+                        acc += c;
+                    }
+                    sBk[NLEV_MAX + 1] = acc;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 2 * PPT; ++k) {
+                    const uint32_t rv = run[k];
+                    if (!rv) continue;
+                    const uint32_t len = rv >> 8;
+                    const uint32_t pos = atomicAdd(&sBk[len], 1u);
+                    const uint32_t j = static_cast<uint32_t>((k >> 1) * NT + tid);
+                    const uint32_t d = j | (static_cast<uint32_t>(k & 1) << 12) | ((rv & 0xffu) << 13) | (len << 20);
+                    if (pos < static_cast<uint32_t>(DCAP)) {
+                        sDesc[pos] = d;
+                    } else {
+                        // more runs than the sort buffer holds: vote this one here
+                        const uint32_t xy = sRidXY[j], q = sRidQ[j];
+                        const int x = xy & 0xffffu, y = xy >> 16;
+                        const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
+                        const int s = (k & 1) ? -1 : 1;
+                        const int la = l0 + static_cast<int>(rv & 0xffu);
                         int accx = la * qx + 8192, accy = la * qy + 8192;
                         int base = (la - l0) * plane;
-                        for (int l = la; l <= lb; ++l) {
+                        for (uint32_t it = 0; it < len; ++it) {
                             const int u = x + s * (accx >> 14) - ax0;
                             const int v = y + s * (accy >> 14) - ay0;
                             if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) &&
@@ -240,6 +328,33 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             accy += qy;
                             base += plane;
                         }
+                    }
+                }
+                __syncthreads();
+                const int nruns = static_cast<int>(min(sBk[NLEV_MAX + 1], static_cast<uint32_t>(DCAP)));
+                for (int k = tid; k < nruns; k += NT) {
+                    const uint32_t d = sDesc[k];
+                    const int j = d & 0xfffu, s = (d >> 12) & 1u ? -1 : 1;
+                    const int la = l0 + static_cast<int>((d >> 13) & 0x7fu);
+                    const int len = static_cast<int>(d >> 20);
+                    const uint32_t xy = sRidXY[j], q = sRidQ[j];
+                    const int x = xy & 0xffffu, y = xy >> 16;
+                    const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
+                    // fixed-point offsets, advanced by q per level; the mirrored vote is
+                    // x - rho(l, q), not x + rho(l, -q) (they differ at exact halves)
+                    int accx = la * qx + 8192, accy = la * qy + 8192;
+                    int base = (la - l0) * plane;
+                    for (int it = 0; it < len; ++it) {
+                        const int u = x + s * (accx >> 14) - ax0;
+                        const int v = y + s * (accy >> 14) - ay0;
+                        if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) &&
+                            static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
+                            const int idx = base + v * AWP + u;
+                            atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
+                        }
+                        accx += qx;
+                        accy += qy;
+                        base += plane;
                     }
                 }
                 __syncthreads();
@@ -329,12 +444,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
                     const int yy = vy + dy;
                     if (yy < ay0 || yy >= ay1) continue;
+                    // row sum over [vx - K, vx + K] clipped to the frame, two taps per step from
+                    // an even column; taps outside the window meet zero weights, the column past
+                    // the region's right edge is zero padding
                     const int xs = max(vx - K, ax0), xe = min(vx + K, ax1 - 1);
-                    const int rowbase = li * plane + (yy - ay0) * AWP - ax0;
-                    const uint16_t* wf = sWt[lg];
+                    const int xw = xs - ((xs - ax0) & 1);
+                    const uint32_t* arow = sA + ((li * plane + (yy - ay0) * AWP) >> 1) + ((xw - ax0) >> 1);
+                    const int o = xw - vx + WB;                   // >= WB - K - 1 >= 0
+                    const uint32_t* wp = (o & 1) ? &sWpO[li][o >> 1] : &sWpE[li][o >> 1];
+                    const int nw = ((xe - xw) >> 1) + 1;
                     uint32_t rs = 0;
-                    for (int x = xs; x <= xe; ++x) rs += static_cast<uint32_t>(wf[abs(x - vx)]) * get_u16(sA, rowbase + x);
-                    if (rs) atomicAdd(&sHS[h], static_cast<unsigned long long>(wf[dy < 0 ? -dy : dy]) * rs);
+                    for (int k = 0; k < nw; ++k) rs = dot2_u16(arow[k], wp[k], rs);
+                    if (rs) atomicAdd(&sHS[h], static_cast<unsigned long long>(sWt[lg][dy < 0 ? -dy : dy]) * rs);
                 }
                 __syncthreads();
                 for (int h = tid; h < nh; h += NT) {
@@ -464,7 +585,7 @@ hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* r
 
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax) {
     const int side = tile + 2 + 2 * kmax;
-    const size_t plane = (size_t)((side + 7) & ~7) * side;
+    const size_t plane = (size_t)((side + 8) & ~7) * side;
     return ((nlev_max * plane * 2 + 15) / 16) * 16;
 }
 
