@@ -126,6 +126,45 @@ void rd_destroy(rd_handle h);
 rd_status rd_detect(rd_handle h, const rd_frame* frame, const rd_params* params,
                     rd_ring* out, int32_t capacity, int32_t* n_rings);
 
+/* ---- batches: many frames in one launch sequence ---------------------------------- */
+
+/* The full pipeline on n frames (1 <= n <= rd_create_info.max_frames, total pixels <=
+ * max_batch_pixels; all frames of one dtype; sizes may differ).  The frames are described
+ * to the kernels by a device-side table; every kernel runs once for the whole batch (the
+ * vote kernel's blocks are persistent and take tiles of any frame from a queue), and the
+ * launch sequence is captured in a HIP graph and replayed while the batch layout (frame
+ * count, tile counts, dtype, parameters' level chunks, tuning) stays the same.  Rings of
+ * frame i go to out[out_offsets[i] ...] (at most capacities[i], host memory), n_rings[i]
+ * receives the count (ascending (r_bin, b, a)).  Results are bit-identical to calling
+ * rd_detect on each frame.  RD_E_TRUNCATED if any frame's capacity was too small. */
+rd_status rd_detect_batch(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params,
+                          rd_ring* out, const int64_t* out_offsets, const int32_t* capacities,
+                          int32_t* n_rings);
+
+/* Launch configuration choices.  None changes any result. */
+typedef struct {
+    int32_t stencil_tile;  /* ridge kernel tile: 0 = 64x32 (64x16 when ceil(4 sigma) > 8),
+                              1 = 32x32, 2 = 64x16                                          */
+    int32_t vote_lds_kb;   /* LDS for one tile's vote histograms, 16..56 (KiB); more levels
+                              per pass with more LDS                                         */
+    int32_t use_graph;     /* 1: capture and replay launch sequences as HIP graphs (needs a
+                              non-null stream)                                               */
+} rd_tuning;
+
+rd_status rd_set_tuning(rd_handle h, const rd_tuning* t);
+rd_status rd_get_tuning(rd_handle h, rd_tuning* t);
+
+/* Time every rd_tuning choice on the given batch (reps timed runs each, after one warm-up),
+ * keep the fastest in the context and return it in *best (may be NULL). */
+rd_status rd_autotune(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params,
+                      int32_t reps, rd_tuning* best);
+
+/* Counters of the last detection call (any entry point that ran the vote kernel):
+ * [0] ridge pixels, [1] votes cast into the frame, [2] hotspots (A > T_int, counted once
+ * per level chunk that scores them), [3] smoothing taps evaluated, [4] above-threshold
+ * voxels, [5] peaks. */
+rd_status rd_read_stats(rd_handle h, int64_t* stats6);
+
 /* ---- kernel timing (measurement) ---------------------------------------------------- */
 
 /* Turn per-kernel timing on (1) or off (0).  When on, detection calls record HIP events on

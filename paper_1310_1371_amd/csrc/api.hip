@@ -1,7 +1,9 @@
 // Host runtime and C ABI of the ridge-directed Hough library: parameter validation, the
 // per-level tables (window half-widths, fixed-point weights, score thresholds, level
-// chunks), context-owned device scratch and the launch sequence of each entry point.
+// chunks), context-owned device scratch, frame-descriptor tables for batches, HIP-graph
+// capture and replay of the launch sequence, tuning and the entry points.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -15,12 +17,19 @@ namespace {
 
 constexpr double TWO_PI = 6.283185307179586;
 constexpr double S_SCALE = 1073741824.0;   // 2^30
-constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per vote work item
-constexpr size_t VOTE_LDS_BUDGET = VOTE_LDS_MAX;
+constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per level chunk
+constexpr int FIT_BLOCKS = 512;
+constexpr int NSTATS = 8;                  // u64: votes, hotspots, strong, taps, ridges
 
 #define RD_HIP(call)                                   \
     do {                                               \
         if ((call) != hipSuccess) return RD_E_DEVICE;  \
+    } while (0)
+
+#define RD_TRY(call)                      \
+    do {                                  \
+        const rd_status st_ = (call);     \
+        if (st_ != RD_OK) return st_;     \
     } while (0)
 
 int gauss_radius(float sigma) { return static_cast<int>(std::ceil(4.0 * static_cast<double>(sigma))); }
@@ -38,7 +47,6 @@ struct LevelTables {
     std::vector<int32_t> ktab;       // L
     std::vector<uint64_t> thr;       // L
     std::vector<int32_t> chunks;     // chunk boundaries over r_min .. r_max + 1
-    int nlev_max = 0, kmax = 0;
     size_t lds = 0;
 };
 
@@ -56,12 +64,11 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
         for (int d = 0; d <= K; ++d)
             t.wtab[static_cast<size_t>(i) * (K_MAX + 1) + d] =
                 static_cast<uint32_t>(std::floor(32768.0 * std::exp(-(double)(d * d) / (2.0 * sg * sg)) + 0.5));
-        t.thr[i] = static_cast<uint64_t>(std::floor(static_cast<double>(p.peak_fraction) * TWO_PI * static_cast<double>(l) * S_SCALE));
+        t.thr[i] = static_cast<uint64_t>(
+            std::floor(static_cast<double>(p.peak_fraction) * TWO_PI * static_cast<double>(l) * S_SCALE));
     }
     // greedy level chunks: peak levels [rc0, rc1) need accumulator levels rc0-1 .. rc1
     t.chunks.clear();
-    t.nlev_max = 0;
-    t.kmax = 0;
     t.lds = 0;
     int rc0 = p.r_min;
     while (rc0 <= p.r_max) {
@@ -70,11 +77,7 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
                vote_lds_bytes(VOTE_TILE, rc1 + 1 - rc0 + 2, t.ktab[rc1 + 1 - t.lbase]) <= budget)
             ++rc1;
         t.chunks.push_back(rc0);
-        const int nlev = rc1 - rc0 + 2;
-        const int kc = t.ktab[rc1 - t.lbase];
-        t.lds = std::max(t.lds, vote_lds_bytes(VOTE_TILE, nlev, kc));
-        t.nlev_max = std::max(t.nlev_max, nlev);
-        t.kmax = std::max(t.kmax, kc);
+        t.lds = std::max(t.lds, vote_lds_bytes(VOTE_TILE, rc1 - rc0 + 2, t.ktab[rc1 - t.lbase]));
         rc0 = rc1;
     }
     t.chunks.push_back(p.r_max + 1);
@@ -82,42 +85,66 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
 
 bool same_params(const rd_params& a, const rd_params& b) { return std::memcmp(&a, &b, sizeof(rd_params)) == 0; }
 
+// Everything a captured launch sequence bakes into its kernel arguments and grids; frame
+// pointers and sizes live in the device-side descriptor table and may change freely.
+struct GraphKey {
+    int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, nchunks = 0, blocks = 0;
+    size_t lds = 0;
+    rd_params params{};
+    bool operator==(const GraphKey& o) const {
+        return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant &&
+               total_tiles == o.total_tiles && total_vtiles == o.total_vtiles && nchunks == o.nchunks &&
+               blocks == o.blocks && lds == o.lds && same_params(params, o.params);
+    }
+};
+
 }  // namespace
 
 struct rd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    int cus = 0;
     int max_w = 0, max_h = 0, max_peaks = 0, max_frames = 0;
     int64_t max_batch_px = 0;
     int64_t max_bins = 0;
     // device scratch
-    void* d_stage = nullptr;            // host-frame staging, max_w * 4 bytes per row
-    uint32_t* d_rxy = nullptr;
+    void* d_stage = nullptr;            // host frames are staged here (4 bytes per pixel)
+    uint32_t* d_rxy = nullptr;          // ridge records, BIN_CAP slots per 16x16 bin
     uint32_t* d_rq = nullptr;
     float* d_rk = nullptr;
     uint32_t* d_bin_count = nullptr;
-    Peak* d_peaks = nullptr;
-    uint32_t* d_counts = nullptr;        // peak counts per frame + overflow flags
-    rd_ring* d_rings = nullptr;
+    Peak* d_peaks = nullptr;            // max_peaks per frame
+    uint32_t* d_counts = nullptr;       // [0, mf) peaks per frame, [mf] bin overflow, [mf+1] vote error,
+                                        // [mf+2] vote tile queue
+    unsigned long long* d_stats = nullptr;
     FrameDesc* d_frames = nullptr;
     uint32_t* d_wtab = nullptr;
     int32_t* d_ktab = nullptr;
     uint64_t* d_thr = nullptr;
     int32_t* d_chunks = nullptr;
-    int64_t* d_offsets = nullptr;        // stage gather offsets (per bin)
-    // pinned host mirrors
+    int64_t* d_offsets = nullptr;       // stage gather offsets (per bin of one frame)
+    // pinned host memory; rings and counts are written by the fit kernel through mappings
     rd_ring* h_rings = nullptr;
+    rd_ring* dh_rings = nullptr;
     uint32_t* h_counts = nullptr;
+    uint32_t* dh_counts = nullptr;
     FrameDesc* h_frames = nullptr;
+    uint64_t* h_stats = nullptr;
     // kernel timing
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
-    // level tables cache
+    // tuning and the cached level tables
+    rd_tuning tune{0, 56, 1};
     rd_params tab_params{};
+    size_t tab_budget = 0;
     bool tab_valid = false;
     LevelTables tabs;
+    // captured launch sequence
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+    int64_t last_stats[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -133,51 +160,65 @@ rd_status check_frame(const rd_ctx* h, const rd_frame* f) {
 }
 
 rd_status upload_tables(rd_ctx* h, const rd_params& p) {
-    if (h->tab_valid && same_params(h->tab_params, p)) return RD_OK;
-    build_tables(p, h->tabs, VOTE_LDS_BUDGET);
+    const size_t budget = static_cast<size_t>(h->tune.vote_lds_kb) * 1024;
+    if (h->tab_valid && same_params(h->tab_params, p) && h->tab_budget == budget) return RD_OK;
+    build_tables(p, h->tabs, budget);
     const LevelTables& t = h->tabs;
     RD_HIP(hipMemcpyAsync(h->d_wtab, t.wtab.data(), t.wtab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
     RD_HIP(hipMemcpyAsync(h->d_ktab, t.ktab.data(), t.ktab.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
     RD_HIP(hipMemcpyAsync(h->d_thr, t.thr.data(), t.thr.size() * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
-    RD_HIP(hipMemcpyAsync(h->d_chunks, t.chunks.data(), t.chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    RD_HIP(hipMemcpyAsync(h->d_chunks, t.chunks.data(), t.chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));   // the host vectors may change on the next call
     h->tab_params = p;
+    h->tab_budget = budget;
     h->tab_valid = true;
     return RD_OK;
 }
 
-// Frame descriptor of a single-frame launch (copies a host frame into the staging buffer).
-rd_status prepare_single(rd_ctx* h, const rd_frame* f, int rg, FrameDesc& fd) {
-    const int64_t esz = f->dtype == RD_U16 ? 2 : 4;
-    fd = FrameDesc{};
-    fd.W = f->width;
-    fd.H = f->height;
-    if (f->on_device) {
-        fd.img = f->data;
-        fd.pitch = f->pitch_bytes;
-    } else {
-        const int64_t pitch = static_cast<int64_t>(h->max_w) * 4;
-        RD_HIP(hipMemcpy2DAsync(h->d_stage, pitch, f->data, f->pitch_bytes, f->width * esz, f->height,
-                                hipMemcpyHostToDevice, h->stream));
-        fd.img = h->d_stage;
-        fd.pitch = pitch;
+int vote_tiles(int W, int H) { return ((W + VOTE_TILE - 1) / VOTE_TILE) * ((H + VOTE_TILE - 1) / VOTE_TILE); }
+
+// Frame descriptors of a launch; host frames are copied into the staging area.
+rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int variant, bool dense, int* total_tiles,
+                       int* total_vtiles) {
+    int tw = 0, th = 0;
+    stencil_tile_dims(variant, rg, dense, &tw, &th);
+    int tt = 0, tv = 0;
+    int64_t bins = 0, staged = 0;
+    for (int i = 0; i < n; ++i) {
+        const rd_frame& f = frames[i];
+        const int64_t esz = f.dtype == RD_U16 ? 2 : 4;
+        FrameDesc fd{};
+        fd.W = f.width;
+        fd.H = f.height;
+        if (f.on_device) {
+            fd.img = f.data;
+            fd.pitch = f.pitch_bytes;
+        } else {
+            char* dst = static_cast<char*>(h->d_stage) + staged;
+            RD_HIP(hipMemcpy2DAsync(dst, f.width * esz, f.data, f.pitch_bytes, f.width * esz, f.height,
+                                    hipMemcpyHostToDevice, h->stream));
+            fd.img = dst;
+            fd.pitch = f.width * esz;
+            staged += ((static_cast<int64_t>(f.width) * f.height * esz + 255) / 256) * 256;
+        }
+        fd.tile0 = tt;
+        fd.vtile0 = tv;
+        fd.bin0 = bins;
+        fd.nbx = (f.width + BIN - 1) / BIN;
+        fd.nby = (f.height + BIN - 1) / BIN;
+        fd.peak0 = i * h->max_peaks;
+        h->h_frames[i] = fd;
+        tt += ((f.width + tw - 1) / tw) * ((f.height + th - 1) / th);
+        tv += vote_tiles(f.width, f.height);
+        bins += static_cast<int64_t>(fd.nbx) * fd.nby;
     }
-    fd.tile0 = 0;
-    fd.vtile0 = 0;
-    fd.bin0 = 0;
-    fd.nbx = (f->width + BIN - 1) / BIN;
-    fd.nby = (f->height + BIN - 1) / BIN;
-    fd.peak0 = 0;
-    (void)rg;
+    if (bins > h->max_bins) return RD_E_TOO_LARGE;
+    RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, n * sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
+    *total_tiles = tt;
+    *total_vtiles = tv;
     return RD_OK;
 }
-
-int stencil_tiles(int W, int H, int rg) {
-    const int tw = stencil_tile_w(), th = stencil_tile_h(rg);
-    return ((W + tw - 1) / tw) * ((H + th - 1) / th);
-}
-
-int vote_tiles(int W, int H) { return ((W + VOTE_TILE - 1) / VOTE_TILE) * ((H + VOTE_TILE - 1) / VOTE_TILE); }
 
 StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_tiles) {
     StencilArgs a{};
@@ -198,6 +239,7 @@ StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_t
     a.rq = h->d_rq;
     a.rk = h->d_rk;
     a.bin_count = h->d_bin_count;
+    a.ridge_total = h->d_stats + 4;
     return a;
 }
 
@@ -222,12 +264,15 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.max_peaks = h->max_peaks;
     a.error = h->d_counts + h->max_frames + 1;
     a.tile_counter = h->d_counts + h->max_frames + 2;
+    a.stats = h->d_stats;
     return a;
 }
 
-FitArgs fit_args(rd_ctx* h, const rd_params& p, int nframes) {
+FitArgs fit_args(rd_ctx* h, const rd_params& p, int nframes, rd_ring* rings, uint32_t* counts_out) {
     FitArgs a{};
     a.frames = h->d_frames;
+    a.counts_out = counts_out;
+    a.error = h->d_counts + h->max_frames + 1;
     a.rxy = h->d_rxy;
     a.bin_count = h->d_bin_count;
     a.peaks = h->d_peaks;
@@ -236,7 +281,7 @@ FitArgs fit_args(rd_ctx* h, const rd_params& p, int nframes) {
     a.max_peaks = h->max_peaks;
     a.w = p.annulus_halfwidth;
     a.min_pts = p.min_fit_points;
-    a.rings = h->d_rings;
+    a.rings = rings;
     return a;
 }
 
@@ -245,7 +290,7 @@ rd_status mark(rd_ctx* h, int i) {
     return RD_OK;
 }
 
-// Called after the stream has been synchronised: adds the elapsed times of the marks.
+// After the stream has been synchronised: add the elapsed times between the marks.
 void collect_timing(rd_ctx* h, bool with_stencil) {
     if (!h->timing) return;
     float ms = 0.f;
@@ -263,48 +308,97 @@ void collect_timing(rd_ctx* h, bool with_stencil) {
     }
 }
 
+// Counters reset, then steps 3-5 (and steps 1-2 when with_stencil).  Kernels only, so the
+// sequence can be captured in a graph.
+rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg, bool with_stencil, int tt, int tv,
+                  rd_ring* rings, uint32_t* counts_out) {
+    RD_HIP(launch_zero(h->d_counts, h->max_frames + 4, h->stream));
+    RD_HIP(launch_zero(reinterpret_cast<uint32_t*>(h->d_stats), 2 * NSTATS, h->stream));
+    if (with_stencil) {
+        RD_TRY(mark(h, 0));
+        RD_HIP(launch_stencil(stencil_args(h, p, nframes, tt), dtype, rg, h->tune.stencil_tile, false, h->stream));
+    }
+    RD_TRY(mark(h, 1));
+    RD_HIP(launch_vote(vote_args(h, p, nframes, tv), h->tabs.lds, false, h->cus, h->stream));
+    RD_TRY(mark(h, 2));
+    RD_HIP(launch_fit(fit_args(h, p, nframes, rings, counts_out), FIT_BLOCKS, h->stream));
+    RD_TRY(mark(h, 3));
+    return RD_OK;
+}
+
+// The pipeline on the frames described in d_frames; results in h_rings / h_counts.
+rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg, int tt, int tv) {
+    const bool graph = h->tune.use_graph && h->stream != nullptr && !h->timing;
+    if (graph) {
+        GraphKey k;
+        k.nframes = nframes;
+        k.dtype = dtype;
+        k.rg = rg;
+        k.variant = h->tune.stencil_tile;
+        k.total_tiles = tt;
+        k.total_vtiles = tv;
+        k.nchunks = static_cast<int>(h->tabs.chunks.size()) - 1;
+        k.blocks = h->cus;
+        k.lds = h->tabs.lds;
+        k.params = p;
+        if (!h->gexec || !(k == h->gkey)) {
+            if (h->gexec) {
+                (void)hipGraphExecDestroy(h->gexec);
+                h->gexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            RD_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            const rd_status st = enqueue(h, p, nframes, dtype, rg, true, tt, tv, h->dh_rings, h->dh_counts);
+            const hipError_t e = hipStreamEndCapture(h->stream, &g);
+            if (st != RD_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return st != RD_OK ? st : RD_E_DEVICE;
+            }
+            const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                h->gexec = nullptr;
+                return RD_E_DEVICE;
+            }
+            h->gkey = k;
+        }
+        RD_HIP(hipGraphLaunch(h->gexec, h->stream));
+    } else {
+        RD_TRY(enqueue(h, p, nframes, dtype, rg, true, tt, tv, h->dh_rings, h->dh_counts));
+    }
+    RD_HIP(hipMemcpyAsync(h->h_stats, h->d_stats, NSTATS * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    collect_timing(h, true);
+    return RD_OK;
+}
+
+void record_stats(rd_ctx* h, int nframes) {
+    int64_t peaks = 0;
+    for (int f = 0; f < nframes; ++f) peaks += std::min<uint32_t>(h->h_counts[f], h->max_peaks);
+    h->last_stats[0] = static_cast<int64_t>(h->h_stats[4]);
+    h->last_stats[1] = static_cast<int64_t>(h->h_stats[0]);
+    h->last_stats[2] = static_cast<int64_t>(h->h_stats[1]);
+    h->last_stats[3] = static_cast<int64_t>(h->h_stats[3]);
+    h->last_stats[4] = static_cast<int64_t>(h->h_stats[2]);
+    h->last_stats[5] = peaks;
+}
+
 bool ring_less(const rd_ring& x, const rd_ring& y) {
     if (x.r_bin != y.r_bin) return x.r_bin < y.r_bin;
     if (x.b != y.b) return x.b < y.b;
     return x.a < y.a;
 }
 
-// Steps 3-5 of one frame whose ridges are already binned; copies the rings out.
-rd_status vote_fit_collect(rd_ctx* h, const rd_params& p, FrameDesc& fd, rd_ring* out, int32_t capacity,
-                           int32_t* n_rings, bool with_stencil) {
-    const int nvt = vote_tiles(fd.W, fd.H);
-    fd.vtile0 = 0;
-    RD_HIP(hipMemsetAsync(h->d_counts, 0, sizeof(uint32_t), h->stream));
-    RD_HIP(hipMemsetAsync(h->d_counts + h->max_frames + 1, 0, 2 * sizeof(uint32_t), h->stream));
-    VoteArgs va = vote_args(h, p, 1, nvt);
-    rd_status st = mark(h, 1);
-    if (st != RD_OK) return st;
-    RD_HIP(launch_vote(va, h->tabs.lds, false, h->stream));
-    st = mark(h, 2);
-    if (st != RD_OK) return st;
-    FitArgs fa = fit_args(h, p, 1);
-    RD_HIP(launch_fit(fa, 512, h->stream));
-    st = mark(h, 3);
-    if (st != RD_OK) return st;
-    RD_HIP(hipMemcpyAsync(h->h_counts, h->d_counts, (h->max_frames + 2) * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                          h->stream));
-    RD_HIP(hipStreamSynchronize(h->stream));
-    collect_timing(h, with_stencil);
-    const uint32_t np = h->h_counts[0];
-    if (h->h_counts[h->max_frames + 1]) return RD_E_OVERFLOW;
-    if (np > static_cast<uint32_t>(h->max_peaks)) {
-        *n_rings = static_cast<int32_t>(np);
-        return RD_E_OVERFLOW;
-    }
-    if (np) {
-        RD_HIP(hipMemcpyAsync(h->h_rings, h->d_rings, np * sizeof(rd_ring), hipMemcpyDeviceToHost, h->stream));
-        RD_HIP(hipStreamSynchronize(h->stream));
-        std::sort(h->h_rings, h->h_rings + np, ring_less);
-    }
+// Sorts frame f's rings in the pinned buffer and copies them out.
+rd_status copy_rings(rd_ctx* h, int f, rd_ring* out, int32_t capacity, int32_t* n_rings) {
+    const uint32_t np = h->h_counts[f];
     *n_rings = static_cast<int32_t>(np);
+    if (np > static_cast<uint32_t>(h->max_peaks)) return RD_E_OVERFLOW;
+    rd_ring* src = h->h_rings + static_cast<int64_t>(f) * h->max_peaks;
+    std::sort(src, src + np, ring_less);
     const uint32_t ncopy = std::min<uint32_t>(np, static_cast<uint32_t>(std::max(capacity, 0)));
-    if (ncopy) std::memcpy(out, h->h_rings, ncopy * sizeof(rd_ring));
-    return np > static_cast<uint32_t>(std::max(capacity, 0)) ? RD_E_TRUNCATED : RD_OK;
+    if (ncopy) std::memcpy(out, src, ncopy * sizeof(rd_ring));
+    return np > ncopy ? RD_E_TRUNCATED : RD_OK;
 }
 
 rd_status bin_external(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n, int W, int H) {
@@ -325,34 +419,50 @@ rd_status bin_external(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n
     b.bin_count = h->d_bin_count;
     b.overflow = d_flag;
     RD_HIP(launch_bin(b, h->stream));
-    uint32_t* h_flag = h->h_counts + h->max_frames;
-    RD_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    uint32_t flag = 0;
+    RD_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
-    if (*h_flag & 2u) return RD_E_INVALID;
-    if (*h_flag & 1u) return RD_E_OVERFLOW;
+    if (flag & 2u) return RD_E_INVALID;
+    if (flag & 1u) return RD_E_OVERFLOW;
     return RD_OK;
 }
 
 rd_status ridge_setup(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n, int32_t W, int32_t H,
-                      const rd_params* params, FrameDesc& fd) {
+                      const rd_params* params) {
     if (!h || !params) return RD_E_INVALID;
-    rd_status st = rd_validate_params(params);
-    if (st != RD_OK) return st;
+    RD_TRY(rd_validate_params(params));
     if (n < 0 || (n > 0 && (!xy || !q))) return RD_E_INVALID;
     if (W < 32 || H < 32) return RD_E_INVALID;
     if (W > h->max_w || H > h->max_h) return RD_E_TOO_LARGE;
     RD_HIP(hipSetDevice(h->device));
-    st = upload_tables(h, *params);
-    if (st != RD_OK) return st;
-    st = bin_external(h, xy, q, n, W, H);
-    if (st != RD_OK) return st;
-    fd = FrameDesc{};
+    RD_TRY(upload_tables(h, *params));
+    RD_TRY(bin_external(h, xy, q, n, W, H));
+    FrameDesc fd{};
     fd.W = W;
     fd.H = H;
     fd.nbx = (W + BIN - 1) / BIN;
     fd.nby = (H + BIN - 1) / BIN;
-    RD_HIP(hipMemcpyAsync(h->d_frames, &fd, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
+    h->h_frames[0] = fd;
+    RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
     return RD_OK;
+}
+
+rd_status check_batch(rd_ctx* h, const rd_frame* frames, int32_t n) {
+    if (!frames || n < 1) return RD_E_INVALID;
+    if (n > h->max_frames) return RD_E_TOO_LARGE;
+    int64_t px = 0;
+    for (int i = 0; i < n; ++i) {
+        RD_TRY(check_frame(h, &frames[i]));
+        if (frames[i].dtype != frames[0].dtype) return RD_E_INVALID;
+        px += static_cast<int64_t>(frames[i].width) * frames[i].height;
+    }
+    if (px > h->max_batch_px) return RD_E_TOO_LARGE;
+    return RD_OK;
+}
+
+bool valid_tuning(const rd_tuning& t) {
+    return t.stencil_tile >= 0 && t.stencil_tile < STENCIL_VARIANTS && t.vote_lds_kb >= 16 &&
+           t.vote_lds_kb * 1024 <= VOTE_LDS_MAX && (t.use_graph == 0 || t.use_graph == 1);
 }
 
 }  // namespace
@@ -390,16 +500,16 @@ rd_status rd_validate_params(const rd_params* p) {
 
 rd_status rd_level_tables(const rd_params* p, int32_t capacity_levels, int32_t* ktab, uint32_t* wtab,
                           uint64_t* thr) {
-    rd_status st = rd_validate_params(p);
-    if (st != RD_OK) return st;
+    RD_TRY(rd_validate_params(p));
     LevelTables t;
-    build_tables(*p, t, VOTE_LDS_BUDGET);
+    build_tables(*p, t, VOTE_LDS_MAX);
     if (capacity_levels < t.L) return RD_E_TRUNCATED;
     for (int i = 0; i < t.L; ++i) {
         if (ktab) ktab[i] = t.ktab[i];
         if (thr) thr[i] = t.thr[i];
         if (wtab)
-            for (int d = 0; d <= K_MAX; ++d) wtab[i * (K_MAX + 1) + d] = t.wtab[static_cast<size_t>(i) * (K_MAX + 1) + d];
+            for (int d = 0; d <= K_MAX; ++d)
+                wtab[i * (K_MAX + 1) + d] = t.wtab[static_cast<size_t>(i) * (K_MAX + 1) + d];
     }
     return RD_OK;
 }
@@ -418,11 +528,13 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     if (hipGetDeviceProperties(&prop, info->device) != hipSuccess) return RD_E_DEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RD_E_DEVICE;
     if (hipSetDevice(info->device) != hipSuccess) return RD_E_DEVICE;
+    if (vote_prepare() != hipSuccess) return RD_E_DEVICE;
 
     rd_ctx* h = new (std::nothrow) rd_ctx();
     if (!h) return RD_E_NOMEM;
     h->device = info->device;
     h->stream = static_cast<hipStream_t>(info->stream);
+    h->cus = prop.multiProcessorCount;
     h->max_w = info->max_width;
     h->max_h = info->max_height;
     h->max_peaks = info->max_peaks;
@@ -434,24 +546,29 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
                                                    static_cast<int64_t>(h->max_frames) * (h->max_w / BIN + h->max_h / BIN + 1));
     const int64_t slots = h->max_bins * BIN_CAP;
     const int64_t npk = static_cast<int64_t>(h->max_frames) * h->max_peaks;
+    const int64_t stage_bytes = h->max_batch_px * 4 + static_cast<int64_t>(h->max_frames) * 256;
     bool ok = true;
-    ok = ok && hipMalloc(&h->d_stage, static_cast<size_t>(single) * 4) == hipSuccess;
+    ok = ok && hipMalloc(&h->d_stage, stage_bytes) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_rxy), slots * 4) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_rq), slots * 4) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_rk), slots * 4) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_bin_count), h->max_bins * 4) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_peaks), npk * sizeof(Peak)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_counts), (h->max_frames + 4) * sizeof(uint32_t)) == hipSuccess;
-    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_rings), npk * sizeof(rd_ring)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_stats), NSTATS * sizeof(uint64_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_frames), h->max_frames * sizeof(FrameDesc)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_wtab), (R_LIMIT + 3) * (K_MAX + 1) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_ktab), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_thr), (R_LIMIT + 3) * sizeof(uint64_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_chunks), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_offsets), bins_single * sizeof(int64_t)) == hipSuccess;
-    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_rings), npk * sizeof(rd_ring)) == hipSuccess;
-    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_rings), npk * sizeof(rd_ring), hipHostMallocMapped) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t),
+                             hipHostMallocMapped) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_frames), h->max_frames * sizeof(FrameDesc)) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_stats), NSTATS * sizeof(uint64_t)) == hipSuccess;
+    ok = ok && hipHostGetDevicePointer(reinterpret_cast<void**>(&h->dh_rings), h->h_rings, 0) == hipSuccess;
+    ok = ok && hipHostGetDevicePointer(reinterpret_cast<void**>(&h->dh_counts), h->h_counts, 0) == hipSuccess;
     if (!ok) {
         rd_destroy(h);
         return RD_E_NOMEM;
@@ -465,6 +582,7 @@ void rd_destroy(rd_handle h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     (void)hipFree(h->d_stage);
     (void)hipFree(h->d_rxy);
     (void)hipFree(h->d_rq);
@@ -472,7 +590,7 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_bin_count);
     (void)hipFree(h->d_peaks);
     (void)hipFree(h->d_counts);
-    (void)hipFree(h->d_rings);
+    (void)hipFree(h->d_stats);
     (void)hipFree(h->d_frames);
     (void)hipFree(h->d_wtab);
     (void)hipFree(h->d_ktab);
@@ -484,31 +602,106 @@ void rd_destroy(rd_handle h) {
     if (h->h_rings) (void)hipHostFree(h->h_rings);
     if (h->h_counts) (void)hipHostFree(h->h_counts);
     if (h->h_frames) (void)hipHostFree(h->h_frames);
+    if (h->h_stats) (void)hipHostFree(h->h_stats);
     delete h;
 }
 
 rd_status rd_detect(rd_handle h, const rd_frame* frame, const rd_params* params, rd_ring* out, int32_t capacity,
                     int32_t* n_rings) {
-    if (!h || !params || !n_rings || (capacity > 0 && !out) || capacity < 0) return RD_E_INVALID;
+    if (!h || !params || !n_rings || capacity < 0 || (capacity > 0 && !out)) return RD_E_INVALID;
     *n_rings = 0;
-    rd_status st = rd_validate_params(params);
-    if (st != RD_OK) return st;
-    st = check_frame(h, frame);
-    if (st != RD_OK) return st;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_frame(h, frame));
     RD_HIP(hipSetDevice(h->device));
-    st = upload_tables(h, *params);
-    if (st != RD_OK) return st;
+    RD_TRY(upload_tables(h, *params));
     const int rg = gauss_radius(params->sigma_smooth);
-    FrameDesc fd;
-    st = prepare_single(h, frame, rg, fd);
-    if (st != RD_OK) return st;
-    RD_HIP(hipMemcpyAsync(h->d_frames, &fd, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
-    const int nt = stencil_tiles(fd.W, fd.H, rg);
-    StencilArgs sa = stencil_args(h, *params, 1, nt);
-    st = mark(h, 0);
-    if (st != RD_OK) return st;
-    RD_HIP(launch_stencil(sa, frame->dtype, rg, false, h->stream));
-    return vote_fit_collect(h, *params, fd, out, capacity, n_rings, true);
+    int tt = 0, tv = 0;
+    RD_TRY(setup_frames(h, frame, 1, rg, h->tune.stencil_tile, false, &tt, &tv));
+    RD_TRY(run_pipeline(h, *params, 1, frame->dtype, rg, tt, tv));
+    record_stats(h, 1);
+    if (h->h_counts[1]) return RD_E_OVERFLOW;
+    return copy_rings(h, 0, out, capacity, n_rings);
+}
+
+rd_status rd_detect_batch(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params, rd_ring* out,
+                          const int64_t* out_offsets, const int32_t* capacities, int32_t* n_rings) {
+    if (!h || !params || !out_offsets || !capacities || !n_rings) return RD_E_INVALID;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_batch(h, frames, n));
+    for (int i = 0; i < n; ++i) {
+        n_rings[i] = 0;
+        if (capacities[i] < 0 || (capacities[i] > 0 && !out) || out_offsets[i] < 0) return RD_E_INVALID;
+    }
+    RD_HIP(hipSetDevice(h->device));
+    RD_TRY(upload_tables(h, *params));
+    const int rg = gauss_radius(params->sigma_smooth);
+    int tt = 0, tv = 0;
+    RD_TRY(setup_frames(h, frames, n, rg, h->tune.stencil_tile, false, &tt, &tv));
+    RD_TRY(run_pipeline(h, *params, n, frames[0].dtype, rg, tt, tv));
+    record_stats(h, n);
+    if (h->h_counts[n]) return RD_E_OVERFLOW;
+    rd_status result = RD_OK;
+    for (int i = 0; i < n; ++i) {
+        const rd_status st = copy_rings(h, i, out ? out + out_offsets[i] : nullptr, capacities[i], &n_rings[i]);
+        if (st == RD_E_OVERFLOW) return st;
+        if (st != RD_OK) result = st;
+    }
+    return result;
+}
+
+rd_status rd_set_tuning(rd_handle h, const rd_tuning* t) {
+    if (!h || !t || !valid_tuning(*t)) return RD_E_INVALID;
+    h->tune = *t;
+    return RD_OK;
+}
+
+rd_status rd_get_tuning(rd_handle h, rd_tuning* t) {
+    if (!h || !t) return RD_E_INVALID;
+    *t = h->tune;
+    return RD_OK;
+}
+
+rd_status rd_autotune(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params, int32_t reps,
+                      rd_tuning* best) {
+    if (!h || !params || reps < 1) return RD_E_INVALID;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_batch(h, frames, n));
+    std::vector<int32_t> counts(n), caps(n, 0);
+    std::vector<int64_t> offs(n, 0);
+    const rd_tuning saved = h->tune;
+    rd_tuning winner = saved;
+    double best_s = 1e300;
+    static const int kLds[] = {32, 40, 48, 56};
+    for (int v = 0; v < STENCIL_VARIANTS; ++v) {
+        for (int kb : kLds) {
+            if (kb * 1024 > VOTE_LDS_MAX) continue;
+            h->tune.stencil_tile = v;
+            h->tune.vote_lds_kb = kb;
+            h->tune.use_graph = saved.use_graph;
+            const rd_status st = rd_detect_batch(h, frames, n, params, nullptr, offs.data(), caps.data(), counts.data());
+            if (st != RD_OK && st != RD_E_TRUNCATED) {
+                h->tune = saved;
+                return st;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < reps; ++r)
+                (void)rd_detect_batch(h, frames, n, params, nullptr, offs.data(), caps.data(), counts.data());
+            const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (s < best_s) {
+                best_s = s;
+                winner = h->tune;
+            }
+        }
+    }
+    h->tune = winner;
+    if (best) *best = winner;
+    return RD_OK;
+}
+
+rd_status rd_read_stats(rd_handle h, int64_t* stats6) {
+    if (!h || !stats6) return RD_E_INVALID;
+    for (int i = 0; i < 6; ++i) stats6[i] = h->last_stats[i];
+    return RD_OK;
 }
 
 rd_status rd_enable_timing(rd_handle h, int32_t enable) {
@@ -537,20 +730,17 @@ rd_status rd_read_timing(rd_handle h, double* ms_total, int64_t* launches, int32
 rd_status rd_stage_curvature(rd_handle h, const rd_frame* frame, const rd_params* params, float* k_dev,
                              int16_t* q_dev) {
     if (!h || !params || !k_dev || !q_dev) return RD_E_INVALID;
-    rd_status st = rd_validate_params(params);
-    if (st != RD_OK) return st;
-    st = check_frame(h, frame);
-    if (st != RD_OK) return st;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_frame(h, frame));
     RD_HIP(hipSetDevice(h->device));
     const int rg = gauss_radius(params->sigma_smooth);
-    FrameDesc fd;
-    st = prepare_single(h, frame, rg, fd);
-    if (st != RD_OK) return st;
-    RD_HIP(hipMemcpyAsync(h->d_frames, &fd, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
-    StencilArgs sa = stencil_args(h, *params, 1, stencil_tiles(fd.W, fd.H, rg));
+    int tt = 0, tv = 0;
+    RD_TRY(setup_frames(h, frame, 1, rg, 0, true, &tt, &tv));
+    StencilArgs sa = stencil_args(h, *params, 1, tt);
     sa.k_dense = k_dev;
     sa.q_dense = q_dev;
-    RD_HIP(launch_stencil(sa, frame->dtype, rg, true, h->stream));
+    sa.ridge_total = nullptr;
+    RD_HIP(launch_stencil(sa, frame->dtype, rg, 0, true, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     return RD_OK;
 }
@@ -559,19 +749,17 @@ rd_status rd_stage_ridges(rd_handle h, const rd_frame* frame, const rd_params* p
                           int16_t* q_dev, float* k_dev, int64_t capacity, int64_t* n_ridges) {
     if (!h || !params || !n_ridges || capacity < 0) return RD_E_INVALID;
     *n_ridges = 0;
-    rd_status st = rd_validate_params(params);
-    if (st != RD_OK) return st;
-    st = check_frame(h, frame);
-    if (st != RD_OK) return st;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_frame(h, frame));
     RD_HIP(hipSetDevice(h->device));
     const int rg = gauss_radius(params->sigma_smooth);
-    FrameDesc fd;
-    st = prepare_single(h, frame, rg, fd);
-    if (st != RD_OK) return st;
-    RD_HIP(hipMemcpyAsync(h->d_frames, &fd, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
-    StencilArgs sa = stencil_args(h, *params, 1, stencil_tiles(fd.W, fd.H, rg));
-    RD_HIP(launch_stencil(sa, frame->dtype, rg, false, h->stream));
+    int tt = 0, tv = 0;
+    RD_TRY(setup_frames(h, frame, 1, rg, h->tune.stencil_tile, false, &tt, &tv));
+    StencilArgs sa = stencil_args(h, *params, 1, tt);
+    sa.ridge_total = nullptr;
+    RD_HIP(launch_stencil(sa, frame->dtype, rg, h->tune.stencil_tile, false, h->stream));
     // per-bin counts -> offsets on the host (a debug path), then one gather kernel
+    const FrameDesc& fd = h->h_frames[0];
     const int64_t nbins = static_cast<int64_t>(fd.nbx) * fd.nby;
     std::vector<uint32_t> cnt(nbins);
     RD_HIP(hipMemcpyAsync(cnt.data(), h->d_bin_count, nbins * 4, hipMemcpyDeviceToHost, h->stream));
@@ -587,7 +775,7 @@ rd_status rd_stage_ridges(rd_handle h, const rd_frame* frame, const rd_params* p
     if (tot == 0) return RD_OK;
     RD_HIP(hipMemcpyAsync(h->d_offsets, off.data(), nbins * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
     RD_HIP(launch_gather(h->d_rxy, h->d_rq, h->d_rk, h->d_bin_count, h->d_offsets, nbins, xy_dev, q_dev, k_dev,
-                            h->stream));
+                         h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     return RD_OK;
 }
@@ -595,21 +783,19 @@ rd_status rd_stage_ridges(rd_handle h, const rd_frame* frame, const rd_params* p
 rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev, int64_t n, int32_t width,
                               int32_t height, const rd_params* params, uint32_t* acc_dev, uint64_t* score_dev) {
     if (!acc_dev) return RD_E_INVALID;
-    FrameDesc fd;
-    rd_status st = ridge_setup(h, xy_dev, q_dev, n, width, height, params, fd);
-    if (st != RD_OK) return st;
+    RD_TRY(ridge_setup(h, xy_dev, q_dev, n, width, height, params));
     const size_t vox = static_cast<size_t>(h->tabs.L) * width * height;
     if (score_dev) RD_HIP(hipMemsetAsync(score_dev, 0, vox * sizeof(uint64_t), h->stream));
-    RD_HIP(hipMemsetAsync(h->d_counts, 0, (h->max_frames + 4) * sizeof(uint32_t), h->stream));
+    RD_HIP(launch_zero(h->d_counts, h->max_frames + 4, h->stream));
     VoteArgs va = vote_args(h, *params, 1, vote_tiles(width, height));
     va.acc_dump = acc_dev;
     va.score_dump = score_dev;
-    RD_HIP(launch_vote(va, h->tabs.lds, true, h->stream));
-    RD_HIP(hipMemcpyAsync(h->h_counts, h->d_counts, (h->max_frames + 2) * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                          h->stream));
+    va.stats = nullptr;
+    RD_HIP(launch_vote(va, h->tabs.lds, true, h->cus, h->stream));
+    uint32_t err = 0;
+    RD_HIP(hipMemcpyAsync(&err, h->d_counts + h->max_frames + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
-    if (h->h_counts[h->max_frames + 1]) return RD_E_OVERFLOW;
-    return RD_OK;
+    return err ? RD_E_OVERFLOW : RD_OK;
 }
 
 rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev, int64_t n, int32_t width,
@@ -617,10 +803,14 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
                            int32_t* n_rings) {
     if (!n_rings || capacity < 0 || (capacity > 0 && !out)) return RD_E_INVALID;
     *n_rings = 0;
-    FrameDesc fd;
-    rd_status st = ridge_setup(h, xy_dev, q_dev, n, width, height, params, fd);
-    if (st != RD_OK) return st;
-    return vote_fit_collect(h, *params, fd, out, capacity, n_rings, false);
+    RD_TRY(ridge_setup(h, xy_dev, q_dev, n, width, height, params));
+    RD_TRY(enqueue(h, *params, 1, RD_F32, 0, false, 0, vote_tiles(width, height), h->dh_rings, h->dh_counts));
+    RD_HIP(hipMemcpyAsync(h->h_stats, h->d_stats, NSTATS * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    collect_timing(h, false);
+    record_stats(h, 1);
+    if (h->h_counts[1]) return RD_E_OVERFLOW;
+    return copy_rings(h, 0, out, capacity, n_rings);
 }
 
 }  // extern "C"

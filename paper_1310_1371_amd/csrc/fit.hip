@@ -47,6 +47,10 @@ __device__ bool solve3(double M[3][3], double rhs[3], double x[3]) {
 
 __global__ __launch_bounds__(64) void k_fit(FitArgs a) {
     const int lane = threadIdx.x;
+    if (blockIdx.x == 0 && lane == 0 && a.counts_out) {
+        for (int f = 0; f < a.nframes; ++f) a.counts_out[f] = a.peak_count[f];
+        a.counts_out[a.nframes] = a.error ? *a.error : 0u;
+    }
     for (int f = 0; f < a.nframes; ++f) {
         const FrameDesc fd = a.frames[f];
         const uint32_t np = min(a.peak_count[f], static_cast<uint32_t>(a.max_peaks));

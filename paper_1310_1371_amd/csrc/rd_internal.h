@@ -50,6 +50,7 @@ struct StencilArgs {
     uint32_t* bin_count;     // ridges per bin
     float* k_dense;          // dense outputs (stage mode, single frame)
     int16_t* q_dense;
+    unsigned long long* ridge_total;   // statistics: ridges found (may be null)
 };
 
 struct VoteArgs {
@@ -72,12 +73,15 @@ struct VoteArgs {
     int32_t max_peaks;           // per frame
     uint32_t* error;             // bit 0: a work item had more strong voxels than it holds
     uint32_t* tile_counter;      // work queue of vote tiles (zero before the launch)
+    unsigned long long* stats;   // [votes, hotspots, strong] accumulated (may be null)
     uint32_t* acc_dump;          // stage mode (single frame): dense [L][H][W]
     uint64_t* score_dump;
 };
 
 struct FitArgs {
     const FrameDesc* frames;
+    uint32_t* counts_out;        // per frame ring count, then the vote error flag (host mapped)
+    const uint32_t* error;
     const uint32_t* rxy;
     const uint32_t* bin_count;
     const Peak* peaks;
@@ -102,15 +106,19 @@ struct BinArgs {
 };
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, bool dense, hipStream_t s);
-int stencil_tile_w();
-int stencil_tile_h(int rg);
+// stencil tile shapes: variant 0 = 64 x 32 (64 x 16 for Gaussian radius > 8), 1 = 32 x 32,
+// 2 = 64 x 16; the dense stage output always uses variant 0
+constexpr int STENCIL_VARIANTS = 3;
+void stencil_tile_dims(int variant, int rg, bool dense, int* tw, int* th);
+hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, int variant, bool dense, hipStream_t s);
 
 constexpr int VOTE_TILE = 32;
 constexpr int VOTE_LDS_MAX = 56 * 1024;   // with ~101 KB of static LDS: ~157 KB of 160   // dynamic LDS of the vote kernel (histogram)
 constexpr int VOTE_NLEV_MAX = 12;          // accumulator levels per level chunk
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
-hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, hipStream_t s);
+hipError_t vote_prepare();   // one-time kernel attributes (outside any graph capture)
+hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s);
+hipError_t launch_zero(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s);
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* rk, const uint32_t* bin_count,

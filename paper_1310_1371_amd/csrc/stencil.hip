@@ -272,6 +272,7 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
                     uint32_t tot = 0;
                     for (int w2 = 0; w2 < NT / 64; ++w2) tot += wcount[j][w2];
                     a.bin_count[bin] = tot;
+                    if (tot && a.ridge_total) atomicAdd(a.ridge_total, static_cast<unsigned long long>(tot));
                 }
             }
         }
@@ -279,32 +280,50 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
     }
 }
 
-template <typename TIN, int RG, bool DENSE>
+template <typename TIN, int TW, int TH, int RG, bool DENSE>
 hipError_t launch_t(const StencilArgs& a, hipStream_t s) {
-    using SH = StencilShape<64, (RG <= 8 ? 32 : 16), RG>;
-    const int blocks = a.total_tiles;
-    hipLaunchKernelGGL((k_stencil<TIN, SH, DENSE>), dim3(blocks), dim3(NT), 0, s, a);
+    using SH = StencilShape<TW, TH, RG>;
+    hipLaunchKernelGGL((k_stencil<TIN, SH, DENSE>), dim3(a.total_tiles), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename TIN, bool DENSE>
-hipError_t launch_rg(const StencilArgs& a, int rg, hipStream_t s) {
-    if (rg <= 4) return launch_t<TIN, 4, DENSE>(a, s);
-    if (rg <= 8) return launch_t<TIN, 8, DENSE>(a, s);
-    if (rg <= 12) return launch_t<TIN, 12, DENSE>(a, s);
-    return launch_t<TIN, 16, DENSE>(a, s);
+template <typename TIN, int RG>
+hipError_t launch_shape(const StencilArgs& a, int variant, bool dense, hipStream_t s) {
+    if (dense) return launch_t<TIN, 64, (RG <= 8 ? 32 : 16), RG, true>(a, s);   // stage output
+    switch (variant) {
+        case 1: return launch_t<TIN, 32, 32, RG, false>(a, s);
+        case 2: return launch_t<TIN, 64, 16, RG, false>(a, s);
+        default: return launch_t<TIN, 64, (RG <= 8 ? 32 : 16), RG, false>(a, s);
+    }
+}
+
+template <typename TIN>
+hipError_t launch_rg(const StencilArgs& a, int rg, int variant, bool dense, hipStream_t s) {
+    if (rg <= 4) return launch_shape<TIN, 4>(a, variant, dense, s);
+    if (rg <= 8) return launch_shape<TIN, 8>(a, variant, dense, s);
+    if (rg <= 12) return launch_shape<TIN, 12>(a, variant, dense, s);
+    return launch_shape<TIN, 16>(a, variant, dense, s);
 }
 
 }  // namespace
 
-int stencil_tile_w() { return 64; }
-int stencil_tile_h(int rg) { return rg <= 8 ? 32 : 16; }
-
-hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, bool dense, hipStream_t s) {
-    if (dtype == RD_U16) {
-        return dense ? launch_rg<uint16_t, true>(a, rg, s) : launch_rg<uint16_t, false>(a, rg, s);
+void stencil_tile_dims(int variant, int rg, bool dense, int* tw, int* th) {
+    if (dense || variant == 0) {
+        *tw = 64;
+        *th = rg <= 8 ? 32 : 16;
+    } else if (variant == 1) {
+        *tw = 32;
+        *th = 32;
+    } else {
+        *tw = 64;
+        *th = 16;
     }
-    return dense ? launch_rg<float, true>(a, rg, s) : launch_rg<float, false>(a, rg, s);
+}
+
+hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, int variant, bool dense, hipStream_t s) {
+    if (a.total_tiles <= 0) return hipSuccess;
+    if (dtype == RD_U16) return launch_rg<uint16_t>(a, rg, variant, dense, s);
+    return launch_rg<float>(a, rg, variant, dense, s);
 }
 
 }  // namespace rd

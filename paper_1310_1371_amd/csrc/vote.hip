@@ -125,6 +125,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     const int lbase = a.lbase;
     const int r_lo = sChunk[0], r_hi = sChunk[a.nchunks];     // peak levels [r_lo, r_hi)
     const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
+    unsigned long long st_votes = 0, st_hot = 0, st_strong = 0, st_taps = 0;   // statistics
 
     for (;;) {
         // tiles are taken from a queue: their cost varies with the number of hotspots
@@ -323,6 +324,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                                 static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
                                 const int idx = base + v * AWP + u;
                                 atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
+                                ++st_votes;
                             }
                             accx += qx;
                             accy += qy;
@@ -351,6 +353,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
                             const int idx = base + v * AWP + u;
                             atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
+                            ++st_votes;
                         }
                         accx += qx;
                         accy += qy;
@@ -455,6 +458,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int nw = ((xe - xw) >> 1) + 1;
                     uint32_t rs = 0;
                     for (int k = 0; k < nw; ++k) rs = dot2_u16(arow[k], wp[k], rs);
+                    st_taps += 2 * nw;
                     if (rs) atomicAdd(&sHS[h], static_cast<unsigned long long>(sWt[lg][dy < 0 ? -dy : dy]) * rs);
                 }
                 __syncthreads();
@@ -483,6 +487,10 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
 
             // ---- 3x3x3 comparison of the strong voxels of the peak levels [rc0, rc1)
             const int ns = static_cast<int>(min(sNs, static_cast<uint32_t>(SCAP)));
+            if (tid == 0) {
+                st_hot += nh_all;
+                st_strong += static_cast<unsigned long long>(ns);
+            }
             for (int j = tid; j < ns; j += NT) {
                 const uint32_t e = sStrongId[j];
                 const int li = e >> 16, sidx = e & 0xffff;
@@ -525,6 +533,22 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 sMap[(e >> 16) * SR2 + (e & 0xffff)] = 0;
             }
             __syncthreads();
+        }
+    }
+    if (a.stats) {
+        unsigned long long v = st_votes, tp = st_taps;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            v += __shfl_xor(v, o, 64);
+            tp += __shfl_xor(tp, o, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(&a.stats[0], v);
+            atomicAdd(&a.stats[3], tp);
+        }
+        if (tid == 0) {
+            atomicAdd(&a.stats[1], st_hot);
+            atomicAdd(&a.stats[2], st_strong);
         }
     }
 }
@@ -589,32 +613,33 @@ size_t vote_lds_bytes(int tile, int nlev_max, int kmax) {
     return ((nlev_max * plane * 2 + 15) / 16) * 16;
 }
 
-static bool g_attr_set[2] = {false, false};
-static int g_cus = 0;
+hipError_t vote_prepare() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
+}
 
-hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, hipStream_t s) {
-    const int items = a.total_vtiles;
-    if (items <= 0 || a.nchunks <= 0) return hipSuccess;
-    if (!g_cus) {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-    }
-    const int blocks = items < g_cus ? items : g_cus;   // persistent: one block per CU, a tile per step
-    const void* fn = dump ? reinterpret_cast<const void*>(&k_vote<VOTE_TILE, true>)
-                          : reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false>);
-    bool& set = g_attr_set[dump ? 1 : 0];
-    if (!set) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
-        if (e != hipSuccess) return e;
-        set = true;
-    }
+hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s) {
+    if (a.total_vtiles <= 0 || a.nchunks <= 0) return hipSuccess;
+    if (blocks > a.total_vtiles) blocks = a.total_vtiles;   // persistent blocks take tiles from the queue
     if (dump)
         hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(blocks), dim3(NT), lds, s, a);
     else
         hipLaunchKernelGGL((k_vote<VOTE_TILE, false>), dim3(blocks), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(uint32_t* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Zeroing by a kernel rather than a memset node keeps captured graphs replay-safe.
+hipError_t launch_zero(uint32_t* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

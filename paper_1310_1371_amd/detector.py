@@ -106,6 +106,53 @@ class Detector:
         N.check(st, "rd_detect_ridges")
         return rings_to_numpy(self._rings, n.value)
 
+    # -------------------------------------------------------------------- batches
+    def _frame_array(self, frames):
+        n = len(frames)
+        arr = (N.RdFrame * n)()
+        for i, f in enumerate(frames):
+            arr[i] = _frame_struct(f)
+        return arr
+
+    def detect_batch(self, frames, params: dict, capacity_per_frame: int | None = None) -> list:
+        """Rings of every frame of a list (numpy arrays or CUDA tensors of one dtype), one launch
+        sequence for the whole batch.  Returns a list of RING_DTYPE arrays."""
+        n = len(frames)
+        arr = self._frame_array(frames)
+        cap = capacity_per_frame or self.max_peaks
+        out = (N.RdRing * (n * cap))()
+        offs = (ctypes.c_int64 * n)(*[i * cap for i in range(n)])
+        caps = (ctypes.c_int32 * n)(*([cap] * n))
+        counts = (ctypes.c_int32 * n)()
+        p = N.make_params(params)
+        st = self._lib.rd_detect_batch(self._h, arr, n, ctypes.byref(p), out, offs, caps, counts)
+        N.check(st, "rd_detect_batch")
+        buf = np.frombuffer(out, dtype=RING_DTYPE)
+        return [buf[i * cap:i * cap + counts[i]].copy() for i in range(n)]
+
+    def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = 56, use_graph: bool = True):
+        t = N.RdTuning(stencil_tile, vote_lds_kb, 1 if use_graph else 0)
+        N.check(self._lib.rd_set_tuning(self._h, ctypes.byref(t)), "rd_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = N.RdTuning()
+        N.check(self._lib.rd_get_tuning(self._h, ctypes.byref(t)), "rd_get_tuning")
+        return dict(stencil_tile=t.stencil_tile, vote_lds_kb=t.vote_lds_kb, use_graph=bool(t.use_graph))
+
+    def autotune(self, frames, params: dict, reps: int = 3) -> dict:
+        arr = self._frame_array(frames)
+        p = N.make_params(params)
+        t = N.RdTuning()
+        N.check(self._lib.rd_autotune(self._h, arr, len(frames), ctypes.byref(p), reps, ctypes.byref(t)),
+                "rd_autotune")
+        return dict(stencil_tile=t.stencil_tile, vote_lds_kb=t.vote_lds_kb, use_graph=bool(t.use_graph))
+
+    def stats(self) -> dict:
+        """Counters of the last call: ridges, votes, hotspots, taps, strong voxels, peaks."""
+        v = (ctypes.c_int64 * 6)()
+        N.check(self._lib.rd_read_stats(self._h, v), "rd_read_stats")
+        return dict(zip(("ridges", "votes", "hotspots", "taps", "strong", "peaks"), list(v)))
+
     # -------------------------------------------------------------------- kernel timing
     def enable_timing(self, on: bool = True):
         N.check(self._lib.rd_enable_timing(self._h, 1 if on else 0), "rd_enable_timing")

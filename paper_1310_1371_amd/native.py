@@ -38,6 +38,10 @@ class RdCreateInfo(ctypes.Structure):
                 ("max_batch_pixels", ctypes.c_int64), ("stream", ctypes.c_void_p)]
 
 
+class RdTuning(ctypes.Structure):
+    _fields_ = [("stencil_tile", ctypes.c_int32), ("vote_lds_kb", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
 class RdError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -57,6 +61,12 @@ SIGNATURES = {
     "rd_create": (ctypes.c_int, [_P(RdCreateInfo), _P(_vp)]),
     "rd_destroy": (None, [_vp]),
     "rd_detect": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _P(RdRing), _i32, _P(_i32)]),
+    "rd_detect_batch": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _P(RdParams), _P(RdRing), _P(_i64), _P(_i32),
+                                       _P(_i32)]),
+    "rd_set_tuning": (ctypes.c_int, [_vp, _P(RdTuning)]),
+    "rd_get_tuning": (ctypes.c_int, [_vp, _P(RdTuning)]),
+    "rd_autotune": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _P(RdParams), _i32, _P(RdTuning)]),
+    "rd_read_stats": (ctypes.c_int, [_vp, _P(_i64)]),
     "rd_enable_timing": (ctypes.c_int, [_vp, _i32]),
     "rd_read_timing": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
     "rd_stage_curvature": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp, _vp]),

@@ -1,0 +1,153 @@
+"""Batched detection (many uneven frames in one launch sequence, graph replay, tuning) against
+per-frame detection on the GPU, and against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ridge_hough as O
+from paper_1310_1371_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _frames_u16():
+    """Four uint16 frames of uneven sizes with the x1000-count ring model."""
+    out = []
+    for i, (W, H, n) in enumerate(((300, 170, 12), (512, 512, 60), (640, 480, 80), (1024, 768, 150))):
+        f = synth.config2(seed=300 + i, W=W, H=H, n_rings=n)
+        out.append(f)
+    return out
+
+
+@pytest.fixture(scope="module")
+def bdet():
+    from paper_1310_1371_amd.detector import Detector
+    d = Detector(max_width=2048, max_height=2048, max_peaks=16384, max_frames=8,
+                 max_batch_pixels=8 * 2048 * 1088)
+    yield d
+    d.close()
+
+
+def _same(a, b):
+    return a.tobytes() == b.tobytes()
+
+
+def test_batch_equals_per_frame(bdet):
+    say("[batch] 4 uneven u16 frames vs per-frame")
+    fs = _frames_u16()
+    p = fs[0].params
+    frames = [torch.from_numpy(f.image).cuda() for f in fs]
+    batch = bdet.detect_batch(frames, p)
+    for f, fr, got in zip(fs, frames, batch):
+        ref = bdet.detect(fr, p)
+        assert _same(ref, got), (f.image.shape, len(ref), len(got))
+        say(f"  {f.image.shape}: {len(got)} rings")
+
+
+def test_batch_graph_replay_uses_new_data(bdet):
+    say("[batch] graph replay with new frame contents")
+    bdet.set_tuning(use_graph=True)
+    fs = _frames_u16()
+    p = fs[0].params
+    bufs = [torch.from_numpy(f.image).cuda() for f in fs]
+    first = bdet.detect_batch(bufs, p)
+    again = bdet.detect_batch(bufs, p)
+    assert all(_same(a, b) for a, b in zip(first, again))
+    # same shapes, different contents, same device buffers: the replayed graph must see them
+    fs2 = [synth.config2(seed=400 + i, W=f.width, H=f.height, n_rings=40) for i, f in enumerate(fs)]
+    for buf, f in zip(bufs, fs2):
+        buf.copy_(torch.from_numpy(f.image).cuda())
+    torch.cuda.synchronize()
+    replay = bdet.detect_batch(bufs, p)
+    bdet.set_tuning(use_graph=False)
+    direct = bdet.detect_batch(bufs, p)
+    bdet.set_tuning(use_graph=True)
+    for a, b, f in zip(replay, direct, fs2):
+        assert _same(a, b)
+    # and they agree with the oracle on a small frame
+    ref = O.detect(fs2[0].image, p)
+    kr = {(int(r["a"]), int(r["b"]), int(r["r_bin"])) for r in ref}
+    kg = {(int(r["a"]), int(r["b"]), int(r["r_bin"])) for r in replay[0]}
+    assert len(kr ^ kg) <= max(1, 0.01 * len(kr))
+
+
+def test_batch_host_frames(bdet):
+    say("[batch] host frames")
+    fs = _frames_u16()[:2]
+    p = fs[0].params
+    host = bdet.detect_batch([f.image for f in fs], p)
+    dev = bdet.detect_batch([torch.from_numpy(f.image).cuda() for f in fs], p)
+    assert all(_same(a, b) for a, b in zip(host, dev))
+
+
+@pytest.mark.parametrize("stencil_tile", [0, 1, 2])
+@pytest.mark.parametrize("vote_lds_kb", [24, 40, 56])
+def test_tuning_invariance(bdet, stencil_tile, vote_lds_kb):
+    say(f"[tuning] stencil {stencil_tile} lds {vote_lds_kb}")
+    f = synth.config2(seed=77, W=640, H=480, n_rings=80)
+    img = torch.from_numpy(f.image).cuda()
+    bdet.set_tuning(stencil_tile=0, vote_lds_kb=56, use_graph=True)
+    ref = bdet.detect(img, f.params)
+    xy0, q0, _ = bdet.ridges(img, f.params)
+    bdet.set_tuning(stencil_tile=stencil_tile, vote_lds_kb=vote_lds_kb, use_graph=True)
+    got = bdet.detect(img, f.params)
+    xy1, q1, _ = bdet.ridges(img, f.params)
+    bdet.set_tuning(stencil_tile=0, vote_lds_kb=56, use_graph=True)
+    assert _same(ref, got)
+    s0 = set(map(tuple, torch.cat([xy0, q0.int()], 1).cpu().numpy().tolist()))
+    s1 = set(map(tuple, torch.cat([xy1, q1.int()], 1).cpu().numpy().tolist()))
+    assert s0 == s1
+
+
+@pytest.mark.parametrize("vote_lds_kb", [16, 32])
+def test_accumulator_invariant_to_level_chunks(bdet, vote_lds_kb):
+    say(f"[tuning] accumulator with lds {vote_lds_kb}")
+    f = synth.config1()
+    p = dict(O.DEFAULTS, **f.params)
+    xs, ys, qx, qy, _ = O.ridges(f.image, p)
+    xy = np.stack([xs, ys], 1).astype(np.int32)
+    q = np.stack([qx, qy], 1).astype(np.int16)
+    bdet.set_tuning(vote_lds_kb=56)
+    a0, s0 = bdet.accumulate(xy, q, 256, 256, p)
+    bdet.set_tuning(vote_lds_kb=vote_lds_kb)
+    a1, s1 = bdet.accumulate(xy, q, 256, 256, p)
+    bdet.set_tuning(vote_lds_kb=56)
+    assert torch.equal(a0, a1) and torch.equal(s0, s1)
+
+
+def test_autotune_returns_a_valid_choice(bdet):
+    say("[tuning] autotune")
+    fs = _frames_u16()[:2]
+    t = bdet.autotune([torch.from_numpy(f.image).cuda() for f in fs], fs[0].params, reps=1)
+    assert t["stencil_tile"] in (0, 1, 2) and 16 <= t["vote_lds_kb"] <= 56
+    bdet.set_tuning(stencil_tile=0, vote_lds_kb=56, use_graph=True)
+
+
+def test_batch_limits(bdet):
+    say("[batch] limits")
+    from paper_1310_1371_amd import native as N
+    f = synth.config1()
+    with pytest.raises(N.RdError) as e:
+        bdet.detect_batch([f.image] * 9, f.params)
+    assert e.value.status == N.RD_E_TOO_LARGE
+    with pytest.raises(N.RdError) as e:
+        bdet.detect_batch([f.image, f.image.astype(np.uint16)], f.params)
+    assert e.value.status == N.RD_E_INVALID
+
+
+def test_stats_counts(bdet):
+    say("[stats]")
+    f = synth.config1()
+    rings = bdet.detect(torch.from_numpy(f.image).cuda(), f.params)
+    st = bdet.stats()
+    xs, ys, qx, qy, _ = O.ridges(f.image, f.params)
+    assert st["peaks"] == len(rings)
+    assert abs(st["ridges"] - len(xs)) <= max(1, 1e-4 * len(xs))
+    assert st["votes"] > 0 and st["hotspots"] > 0 and st["strong"] >= st["peaks"]
