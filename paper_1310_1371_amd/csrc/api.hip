@@ -19,7 +19,7 @@ constexpr double TWO_PI = 6.283185307179586;
 constexpr double S_SCALE = 1073741824.0;   // 2^30
 constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per level chunk
 constexpr int FIT_BLOCKS = 512;
-constexpr int NSTATS = 8;                  // u64: votes, hotspots, strong, taps, ridges
+constexpr int NSTATS = 8 + 64;             // u64: votes, hotspots, strong, taps, -, -, -, -, 64 ridge stripes
 
 #define RD_HIP(call)                                   \
     do {                                               \
@@ -136,7 +136,7 @@ struct rd_ctx {
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
     // tuning and the cached level tables
-    rd_tuning tune{0, 56, 1};
+    rd_tuning tune{0, 52, 1};
     rd_params tab_params{};
     size_t tab_budget = 0;
     bool tab_valid = false;
@@ -239,7 +239,7 @@ StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_t
     a.rq = h->d_rq;
     a.rk = h->d_rk;
     a.bin_count = h->d_bin_count;
-    a.ridge_total = h->d_stats + 4;
+    a.ridge_total = h->d_stats + 8;
     return a;
 }
 
@@ -375,7 +375,9 @@ rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, in
 void record_stats(rd_ctx* h, int nframes) {
     int64_t peaks = 0;
     for (int f = 0; f < nframes; ++f) peaks += std::min<uint32_t>(h->h_counts[f], h->max_peaks);
-    h->last_stats[0] = static_cast<int64_t>(h->h_stats[4]);
+    int64_t ridges = 0;
+    for (int i = 0; i < 64; ++i) ridges += static_cast<int64_t>(h->h_stats[8 + i]);
+    h->last_stats[0] = ridges;
     h->last_stats[1] = static_cast<int64_t>(h->h_stats[0]);
     h->last_stats[2] = static_cast<int64_t>(h->h_stats[1]);
     h->last_stats[3] = static_cast<int64_t>(h->h_stats[3]);
@@ -671,7 +673,7 @@ rd_status rd_autotune(rd_handle h, const rd_frame* frames, int32_t n, const rd_p
     const rd_tuning saved = h->tune;
     rd_tuning winner = saved;
     double best_s = 1e300;
-    static const int kLds[] = {32, 40, 48, 56};
+    static const int kLds[] = {28, 36, 44, 52};
     for (int v = 0; v < STENCIL_VARIANTS; ++v) {
         for (int kb : kLds) {
             if (kb * 1024 > VOTE_LDS_MAX) continue;

@@ -272,8 +272,13 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
                     uint32_t tot = 0;
                     for (int w2 = 0; w2 < NT / 64; ++w2) tot += wcount[j][w2];
                     a.bin_count[bin] = tot;
-                    if (tot && a.ridge_total) atomicAdd(a.ridge_total, static_cast<unsigned long long>(tot));
                 }
+            }
+            if (tid == 0 && a.ridge_total) {     // statistics, striped over 64 counters
+                uint32_t tot = 0;
+                for (int j = 0; j < NB; ++j)
+                    for (int w2 = 0; w2 < NT / 64; ++w2) tot += wcount[j][w2];
+                if (tot) atomicAdd(&a.ridge_total[t & 63], static_cast<unsigned long long>(tot));
             }
         }
         __syncthreads();   // LDS is reused by the next tile of a persistent block

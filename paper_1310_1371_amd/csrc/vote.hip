@@ -59,12 +59,10 @@ __device__ __forceinline__ uint32_t get_u16(const uint32_t* s, int idx) {
 
 constexpr int LMAX = R_LIMIT + 3;          // levels r_min - 1 .. r_max + 1 at most
 constexpr int NLEV_MAX = VOTE_NLEV_MAX;    // accumulator levels per level chunk
-constexpr int RCAP = 4096;                 // ridge records staged per tile
+constexpr int RCAP = 3072;                 // ridge records staged per tile
 constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the per-level fallback)
 constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
 constexpr int WB = K_MAX + 1;              // centre of the padded weight row
-constexpr int DCAP = HCAP * 3;             // sorted vote runs per pass (in the hotspot bytes)
-constexpr int PPT = RCAP / NT;             // staged ridges per thread
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
 
@@ -86,12 +84,12 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ uint16_t sMap[NLEV_MAX * SR2];                // strong index + 1 per score voxel
     __shared__ uint32_t sRidXY[RCAP];
     __shared__ uint32_t sRidQ[RCAP];
-    // hotspot list and scores; while voting, the same bytes hold the vote runs
+    __shared__ uint32_t sRidR[RCAP];                         // level ranges of both signs (u8 pairs)
+    // hotspot list and scores
     __shared__ __align__(16) uint8_t sScratch[HCAP * 12];
     uint32_t* const sHot = reinterpret_cast<uint32_t*>(sScratch);                        // (level << 16) | index
     unsigned long long* const sHS = reinterpret_cast<unsigned long long*>(sScratch + HCAP * 4);
-    uint32_t* const sDesc = reinterpret_cast<uint32_t*>(sScratch);                       // runs sorted by length
-    __shared__ uint32_t sBk[NLEV_MAX + 2];                   // runs per length, then offsets
+
     __shared__ unsigned long long sStrongS[SCAP];
     __shared__ uint32_t sStrongId[SCAP];
     __shared__ uint32_t sBinPre[NT + 1];
@@ -224,100 +222,72 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             if (sBinPre[mid] <= g) lo = mid; else hi = mid;
                         }
                         const int64_t slot = (fd.bin0 + sBinId[lo]) * BIN_CAP + (g - sBinPre[lo]);
-                        sRidXY[j] = a.rxy[slot];
-                        sRidQ[j] = a.rq[slot];
+                        const uint32_t xy = a.rxy[slot], q = a.rq[slot];
+                        sRidXY[j] = xy;
+                        sRidQ[j] = q;
+                        // levels (relative to lbase) at which each sign's vote can land in the
+                        // tile's widest accumulator region: |rho - l q / 2^14| <= 1/2 per axis
+                        const int x = xy & 0xffffu, y = xy >> 16;
+                        const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
+                        uint32_t rr = 0;
+#pragma unroll
+                        for (int sg = 0; sg < 2; ++sg) {
+                            const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
+                            float lo_l = static_cast<float>(r_lo - 1), hi_l = static_cast<float>(r_hi);
+                            bool ok = true;
+                            if (sqx != 0) {
+                                const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
+                                float e0 = (static_cast<float>(ux0 - x) - 0.5f) * inv;
+                                float e1 = (static_cast<float>(ux1 - 1 - x) + 0.5f) * inv;
+                                if (sqx < 0) { const float tt = e0; e0 = e1; e1 = tt; }
+                                lo_l = fmaxf(lo_l, e0);
+                                hi_l = fminf(hi_l, e1);
+                            } else {
+                                ok = x >= ux0 && x < ux1;
+                            }
+                            if (sqy != 0) {
+                                const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqy));
+                                float e0 = (static_cast<float>(uy0 - y) - 0.5f) * inv;
+                                float e1 = (static_cast<float>(uy1 - 1 - y) + 0.5f) * inv;
+                                if (sqy < 0) { const float tt = e0; e0 = e1; e1 = tt; }
+                                lo_l = fmaxf(lo_l, e0);
+                                hi_l = fminf(hi_l, e1);
+                            } else {
+                                ok = ok && y >= uy0 && y < uy1;
+                            }
+                            int la = 255, lb = 0;                      // empty
+                            if (ok && lo_l <= hi_l + 2.0f) {
+                                la = max(r_lo - 1, static_cast<int>(floorf(lo_l)) - 1) - lbase;
+                                lb = min(r_hi, static_cast<int>(ceilf(hi_l)) + 1) - lbase;
+                                if (lb < la) { la = 255; lb = 0; }
+                            }
+                            rr |= (static_cast<uint32_t>(la) | (static_cast<uint32_t>(lb) << 8)) << (16 * sg);
+                        }
+                        sRidR[j] = rr;
                     }
                     __syncthreads();
                 }
-                // vote runs: for each staged ridge and sign, the levels whose vote can fall in
-                // this chunk's region.  The runs are bucketed by length (a counting sort in LDS)
-                // so that a wave works on runs of equal length.
-                if (tid < NLEV_MAX + 2) sBk[tid] = 0u;
-                __syncthreads();
-                uint32_t run[2 * PPT];                         // (la - l0) | length << 8
-                const int dlo = max(l0 - 1, 0), dhi = l1 + 1;
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    run[2 * k] = 0u;
-                    run[2 * k + 1] = 0u;
-                    const int j = k * NT + tid;
-                    if (j >= pn) continue;
-                    const uint32_t xy = sRidXY[j];
+                // votes: each staged ridge and sign over its level range, clipped to this chunk;
+                // the region test below rejects the few votes that land in the tile's widest
+                // region but outside this chunk's
+                for (int j = tid; j < pn; j += NT) {
+                    const uint32_t rr = sRidR[j];
+                    const int la0 = static_cast<int>(rr & 0xffu) + lbase, lb0 = static_cast<int>((rr >> 8) & 0xffu) + lbase;
+                    const int la1 = static_cast<int>((rr >> 16) & 0xffu) + lbase, lb1 = static_cast<int>(rr >> 24) + lbase;
+                    const bool any0 = max(la0, l0) <= min(lb0, l1), any1 = max(la1, l0) <= min(lb1, l1);
+                    if (!any0 && !any1) continue;
+                    const uint32_t xy = sRidXY[j], q = sRidQ[j];
                     const int x = xy & 0xffffu, y = xy >> 16;
-                    // |vote - p| is within 0.72 px of the level: distance screen first
-                    const int gx = max(0, max(ax0 - x, x - (ax1 - 1)));
-                    const int gy = max(0, max(ay0 - y, y - (ay1 - 1)));
-                    const int fx = max(abs(x - ax0), abs(x - (ax1 - 1)));
-                    const int fy = max(abs(y - ay0), abs(y - (ay1 - 1)));
-                    if (gx * gx + gy * gy > dhi * dhi || fx * fx + fy * fy < dlo * dlo) continue;
-                    const uint32_t q = sRidQ[j];
                     const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
 #pragma unroll
                     for (int sg = 0; sg < 2; ++sg) {
-                        const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
-                        // |rho - l q / 2^14| <= 1/2 per axis bounds the levels that can land
-                        float lo_l = static_cast<float>(l0), hi_l = static_cast<float>(l1);
-                        bool ok = true;
-                        if (sqx != 0) {
-                            const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
-                            float e0 = (static_cast<float>(ax0 - x) - 0.5f) * inv;
-                            float e1 = (static_cast<float>(ax1 - 1 - x) + 0.5f) * inv;
-                            if (sqx < 0) { const float tt = e0; e0 = e1; e1 = tt; }
-                            lo_l = fmaxf(lo_l, e0);
-                            hi_l = fminf(hi_l, e1);
-                        } else {
-                            ok = x >= ax0 && x < ax1;
-                        }
-                        if (sqy != 0) {
-                            const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqy));
-                            float e0 = (static_cast<float>(ay0 - y) - 0.5f) * inv;
-                            float e1 = (static_cast<float>(ay1 - 1 - y) + 0.5f) * inv;
-                            if (sqy < 0) { const float tt = e0; e0 = e1; e1 = tt; }
-                            lo_l = fmaxf(lo_l, e0);
-                            hi_l = fminf(hi_l, e1);
-                        } else {
-                            ok = ok && y >= ay0 && y < ay1;
-                        }
-                        if (!ok || !(lo_l <= hi_l + 2.0f)) continue;
-                        const int la = max(l0, static_cast<int>(floorf(lo_l)) - 1);
-                        const int lb = min(l1, static_cast<int>(ceilf(hi_l)) + 1);
-                        if (lb < la) continue;
-                        const int len = lb - la + 1;           // 1 .. nlev <= NLEV_MAX
-                        run[2 * k + sg] = static_cast<uint32_t>(la - l0) | (static_cast<uint32_t>(len) << 8);
-                        atomicAdd(&sBk[len], 1u);
-                    }
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    uint32_t acc = 0;
-                    for (int len = 1; len <= NLEV_MAX; ++len) {
-                        const uint32_t c = sBk[len];
-                        sBk[len] = acc;
-                        acc += c;
-                    }
-                    sBk[NLEV_MAX + 1] = acc;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < 2 * PPT; ++k) {
-                    const uint32_t rv = run[k];
-                    if (!rv) continue;
-                    const uint32_t len = rv >> 8;
-                    const uint32_t pos = atomicAdd(&sBk[len], 1u);
-                    const uint32_t j = static_cast<uint32_t>((k >> 1) * NT + tid);
-                    const uint32_t d = j | (static_cast<uint32_t>(k & 1) << 12) | ((rv & 0xffu) << 13) | (len << 20);
-                    if (pos < static_cast<uint32_t>(DCAP)) {
-                        sDesc[pos] = d;
-                    } else {
-                        // more runs than the sort buffer holds: vote this one here
-                        const uint32_t xy = sRidXY[j], q = sRidQ[j];
-                        const int x = xy & 0xffffu, y = xy >> 16;
-                        const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
-                        const int s = (k & 1) ? -1 : 1;
-                        const int la = l0 + static_cast<int>(rv & 0xffu);
+                        const int la = max(sg ? la1 : la0, l0), lb = min(sg ? lb1 : lb0, l1);
+                        const int s = sg ? -1 : 1;
+                        // fixed-point offsets, advanced by q per level; the mirrored vote is
+                        // x - rho(l, q), not x + rho(l, -q) (they differ at exact halves)
                         int accx = la * qx + 8192, accy = la * qy + 8192;
                         int base = (la - l0) * plane;
-                        for (uint32_t it = 0; it < len; ++it) {
+                        for (int l = la; l <= lb; ++l) {
                             const int u = x + s * (accx >> 14) - ax0;
                             const int v = y + s * (accy >> 14) - ay0;
                             if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) &&
@@ -330,34 +300,6 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             accy += qy;
                             base += plane;
                         }
-                    }
-                }
-                __syncthreads();
-                const int nruns = static_cast<int>(min(sBk[NLEV_MAX + 1], static_cast<uint32_t>(DCAP)));
-                for (int k = tid; k < nruns; k += NT) {
-                    const uint32_t d = sDesc[k];
-                    const int j = d & 0xfffu, s = (d >> 12) & 1u ? -1 : 1;
-                    const int la = l0 + static_cast<int>((d >> 13) & 0x7fu);
-                    const int len = static_cast<int>(d >> 20);
-                    const uint32_t xy = sRidXY[j], q = sRidQ[j];
-                    const int x = xy & 0xffffu, y = xy >> 16;
-                    const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
-                    // fixed-point offsets, advanced by q per level; the mirrored vote is
-                    // x - rho(l, q), not x + rho(l, -q) (they differ at exact halves)
-                    int accx = la * qx + 8192, accy = la * qy + 8192;
-                    int base = (la - l0) * plane;
-                    for (int it = 0; it < len; ++it) {
-                        const int u = x + s * (accx >> 14) - ax0;
-                        const int v = y + s * (accy >> 14) - ay0;
-                        if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) &&
-                            static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
-                            const int idx = base + v * AWP + u;
-                            atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
-                            ++st_votes;
-                        }
-                        accx += qx;
-                        accy += qy;
-                        base += plane;
                     }
                 }
                 __syncthreads();
@@ -378,6 +320,11 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const uint32_t li = __umulhi(rl, mS), r = rl - li * SHh;
                     const int vy = sy0 + static_cast<int>(r);
                     const uint4 w4 = a4[((li * plane + (vy - ay0) * AWP) >> 3) + c8];
+                    // largest of the eight counters by packed 16-bit maxima first
+                    const ushort2_t m2 = __builtin_elementwise_max(
+                        __builtin_elementwise_max(__builtin_bit_cast(ushort2_t, w4.x), __builtin_bit_cast(ushort2_t, w4.y)),
+                        __builtin_elementwise_max(__builtin_bit_cast(ushort2_t, w4.z), __builtin_bit_cast(ushort2_t, w4.w)));
+                    if (static_cast<uint32_t>(m2.x > m2.y ? m2.x : m2.y) <= tint) continue;
                     const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
                     uint32_t hotmask = 0;
 #pragma unroll
