@@ -25,7 +25,9 @@
  *   - "device pointer" arguments are HIP device memory owned by the caller; the work is
  *     ordered on the stream given to rd_create and has completed when the call returns.
  *   - Host arrays are owned by the caller.  The context owns all of its device scratch,
- *     allocated in rd_create; no detection call allocates device memory.
+ *     allocated in rd_create; no detection call allocates device memory.  (The
+ *     differentiable entry points at the end allocate their own scratch once, on the first
+ *     such call, and some of them return as soon as their work is enqueued; see there.)
  *   - One context per host thread; calls on one context must not overlap.
  */
 #ifndef RIDGE_DETECT_H
@@ -207,6 +209,87 @@ rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t*
 rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev,
                            int64_t n, int32_t width, int32_t height, const rd_params* params,
                            rd_ring* out, int32_t capacity, int32_t* n_rings);
+
+/* ---- differentiable extension ------------------------------------------------------------
+ *
+ * The paper's votes are integer and its ridge selection is a threshold, so nothing of
+ * steps 3-5 is differentiable.  These calls relax the vote onto the same ridge set and the
+ * same Hessian (step 1) and fit a ring-intensity profile, with hand-written adjoints:
+ *
+ *   soft accumulator  A~_r(c) = sum over ridges p, s = +-1 of w_p beta(p + s r u_p - c),
+ *                     beta(d) = max(0, 1 - |dx|) max(0, 1 - |dy|), w_p = -k_-(p), u_p the
+ *                     unit eigenvector X_-(p) (continuous, not the step-3 code), radii
+ *                     r_min - 1 .. r_max + 1 as the votes; cells off the frame are dropped.
+ *   ring fit loss     L_j = sum over the window W_j of (I(p) - B_j - A_j g_j(p))^2 with
+ *                     g_j(p) = exp(-(|p - c_j| - r_j)^2 / (2 s^2)); (A_j, B_j) are the
+ *                     least-squares fit at the current ring (c_j, r_j) and
+ *                     W_j = {p : | |p - c0_j| - r0_j | <= 3 s + 2} is fixed by a starting
+ *                     ring (c0_j, r0_j).  The circles of step 5 are the usual start.
+ *
+ * Conventions of this section: all pointers are device pointers owned by the caller;
+ * ring parameters theta are float64 triples (cx, cy, r); the first call of this section on a
+ * context allocates its scratch (about 24 + 100 bytes per pixel of the context's maximum
+ * frame) and returns RD_E_NOMEM if that fails.  Calls that say "enqueued" return once their
+ * kernels are queued on the context's stream; the others return with the work complete.
+ */
+
+/* The ridge set of step 2 (as rd_stage_ridges, bin order) and the Hessian of step 1 at each
+ * ridge pixel: xy_dev int32 (x, y) pairs and hess_dev float64 (Ixx, Iyy, Ixy) triples, each
+ * sized for `capacity` ridges (hess_dev may be NULL).  RD_E_TRUNCATED if the count, written
+ * to *n_ridges, exceeds capacity. */
+rd_status rd_soft_ridges(rd_handle h, const rd_frame* frame, const rd_params* params,
+                         int32_t* xy_dev, double* hess_dev, int64_t capacity, int64_t* n_ridges);
+
+/* The soft accumulator of n ridges (xy_dev, hess_dev as rd_soft_ridges gives them) into
+ * acc_dev, float32 [L][height][width], L = r_max - r_min + 3; every element is written.
+ * RD_E_INVALID if a ridge lies off the frame, RD_E_OVERFLOW if more than 256 ridges fall in
+ * one 16x16 pixel bin (only possible with duplicates). */
+rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess_dev, int64_t n,
+                          int32_t width, int32_t height, const rd_params* params, float* acc_dev);
+
+/* Vector-Jacobian product of rd_soft_forward: given grad_acc_dev = dL/dA~ (float32, shape of
+ * acc_dev), writes grad_hess_dev = dL/d(Ixx, Iyy, Ixy) per ridge (float64 triples).  Through
+ * k_- = X_-^T H X_- and dX_- = (X_+^T dH X_- / (k_- - k_+)) X_+; where the eigenvalues
+ * nearly coincide (|k_+ - k_-| / 2 <= 1e-12 max|H|) the X_- term is dropped and counted in
+ * *n_isotropic (may be NULL: then the call is enqueued). */
+rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hess_dev, int64_t n,
+                           int32_t width, int32_t height, const rd_params* params,
+                           const float* grad_acc_dev, double* grad_hess_dev, int64_t* n_isotropic);
+
+/* Adjoint of step 1's Hessian (Gaussian smoothing, then the 5x5 second-order Sobel kernels
+ * / 64, each 1D pass with reflect-101 borders) applied to per-ridge gradients grad_hess_dev
+ * (float64 triples at xy_dev): ADDS dL/dI into grad_img_dev, float32 [height][width]
+ * contiguous.  The reflect-101 halo is folded back onto the mirrored pixels.  Enqueued. */
+rd_status rd_hessian_backward(rd_handle h, const int32_t* xy_dev, const double* grad_hess_dev,
+                              int64_t n, int32_t width, int32_t height, const rd_params* params,
+                              float* grad_img_dev);
+
+/* Ring fit loss of m rings on one frame (device frame, u16 or f32): loss_dev[j] = L_j
+ * (float64) and, if ab_dev is not NULL, ab_dev[2j..2j+1] = (A_j, B_j).  s > 0 is the
+ * profile width in pixels.  An empty window gives L = 0, A = B = 0; a window where the
+ * profile is constant gives A = 0, B = mean.  Enqueued. */
+rd_status rd_fit_loss(rd_handle h, const rd_frame* frame, const double* theta_dev,
+                      const double* theta0_dev, int64_t m, double s, double* loss_dev,
+                      double* ab_dev);
+
+/* Gradient of sum_j grad_loss_dev[j] L_j: ADDS d/dI into grad_img_dev (float32
+ * [height][width] contiguous; may be NULL) and writes d/dtheta to grad_theta_dev (float64
+ * triples).  (A_j, B_j) sit at their least-squares optimum, so they add no terms.
+ * Enqueued. */
+rd_status rd_fit_loss_backward(rd_handle h, const rd_frame* frame, const double* theta_dev,
+                               const double* theta0_dev, int64_t m, double s,
+                               const double* grad_loss_dev, float* grad_img_dev,
+                               double* grad_theta_dev);
+
+/* Levenberg-Marquardt refinement of m rings over up to 64 device frames (frame_of_dev[j]
+ * = frame of ring j, int32; may be NULL when nframes == 1): from theta0_dev, `iters` steps
+ * of (J^T J + lam diag J^T J) d = -J^T e on the residuals of L_j with (A, B) re-solved at
+ * every point; a step is kept only if it lowers L_j (lam / 3), otherwise lam x 4
+ * (lam starts at 1e-3).  Writes theta_dev and, if not NULL, loss_dev (float64).  Rings
+ * with a frame index outside [0, nframes) get NaN.  Enqueued. */
+rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes,
+                    const int32_t* frame_of_dev, const double* theta0_dev, int64_t m, double s,
+                    int32_t iters, double* theta_dev, double* loss_dev);
 
 #ifdef __cplusplus
 }

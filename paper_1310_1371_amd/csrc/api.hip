@@ -9,7 +9,7 @@
 #include <new>
 #include <vector>
 
-#include "rd_internal.h"
+#include "rd_host.h"
 
 using namespace rd;
 
@@ -21,34 +21,11 @@ constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per level chunk
 constexpr int FIT_BLOCKS = 512;
 constexpr int NSTATS = 8 + 64;             // u64: votes, hotspots, strong, taps, -, -, -, -, 64 ridge stripes
 
-#define RD_HIP(call)                                   \
-    do {                                               \
-        if ((call) != hipSuccess) return RD_E_DEVICE;  \
-    } while (0)
-
-#define RD_TRY(call)                      \
-    do {                                  \
-        const rd_status st_ = (call);     \
-        if (st_ != RD_OK) return st_;     \
-    } while (0)
-
-int gauss_radius(float sigma) { return static_cast<int>(std::ceil(4.0 * static_cast<double>(sigma))); }
-
 double level_sigma(const rd_params& p, int r) {
     return static_cast<double>(p.sig_slope) * r + static_cast<double>(p.sig_icpt);
 }
 
 int level_radius(const rd_params& p, int r) { return static_cast<int>(std::ceil(3.0 * level_sigma(p, r))); }
-
-// Level tables for radii r_min - 1 .. r_max + 1 (index l - (r_min - 1)).
-struct LevelTables {
-    int lbase = 0, L = 0;
-    std::vector<uint32_t> wtab;      // L x (K_MAX + 1)
-    std::vector<int32_t> ktab;       // L
-    std::vector<uint64_t> thr;       // L
-    std::vector<int32_t> chunks;     // chunk boundaries over r_min .. r_max + 1
-    size_t lds = 0;
-};
 
 void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
     t.lbase = p.r_min - 1;
@@ -83,71 +60,13 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
     t.chunks.push_back(p.r_max + 1);
 }
 
-bool same_params(const rd_params& a, const rd_params& b) { return std::memcmp(&a, &b, sizeof(rd_params)) == 0; }
-
-// Everything a captured launch sequence bakes into its kernel arguments and grids; frame
-// pointers and sizes live in the device-side descriptor table and may change freely.
-struct GraphKey {
-    int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, nchunks = 0, blocks = 0;
-    size_t lds = 0;
-    rd_params params{};
-    bool operator==(const GraphKey& o) const {
-        return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant &&
-               total_tiles == o.total_tiles && total_vtiles == o.total_vtiles && nchunks == o.nchunks &&
-               blocks == o.blocks && lds == o.lds && same_params(params, o.params);
-    }
-};
-
 }  // namespace
 
-struct rd_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int cus = 0;
-    int max_w = 0, max_h = 0, max_peaks = 0, max_frames = 0;
-    int64_t max_batch_px = 0;
-    int64_t max_bins = 0;
-    // device scratch
-    void* d_stage = nullptr;            // host frames are staged here (4 bytes per pixel)
-    uint32_t* d_rxy = nullptr;          // ridge records, BIN_CAP slots per 16x16 bin
-    uint32_t* d_rq = nullptr;
-    float* d_rk = nullptr;
-    uint32_t* d_bin_count = nullptr;
-    Peak* d_peaks = nullptr;            // max_peaks per frame
-    uint32_t* d_counts = nullptr;       // [0, mf) peaks per frame, [mf] bin overflow, [mf+1] vote error,
-                                        // [mf+2] vote tile queue
-    unsigned long long* d_stats = nullptr;
-    FrameDesc* d_frames = nullptr;
-    uint32_t* d_wtab = nullptr;
-    int32_t* d_ktab = nullptr;
-    uint64_t* d_thr = nullptr;
-    int32_t* d_chunks = nullptr;
-    int64_t* d_offsets = nullptr;       // stage gather offsets (per bin of one frame)
-    // pinned host memory; rings and counts are written by the fit kernel through mappings
-    rd_ring* h_rings = nullptr;
-    rd_ring* dh_rings = nullptr;
-    uint32_t* h_counts = nullptr;
-    uint32_t* dh_counts = nullptr;
-    FrameDesc* h_frames = nullptr;
-    uint64_t* h_stats = nullptr;
-    // kernel timing
-    bool timing = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    double t_ms[3] = {0, 0, 0};
-    int64_t t_n[3] = {0, 0, 0};
-    // tuning and the cached level tables
-    rd_tuning tune{0, 52, 1};
-    rd_params tab_params{};
-    size_t tab_budget = 0;
-    bool tab_valid = false;
-    LevelTables tabs;
-    // captured launch sequence
-    hipGraphExec_t gexec = nullptr;
-    GraphKey gkey;
-    int64_t last_stats[6] = {0, 0, 0, 0, 0, 0};
-};
+namespace rd {
 
-namespace {
+int gauss_radius(float sigma) { return static_cast<int>(std::ceil(4.0 * static_cast<double>(sigma))); }
+
+int vote_tiles(int W, int H) { return ((W + VOTE_TILE - 1) / VOTE_TILE) * ((H + VOTE_TILE - 1) / VOTE_TILE); }
 
 rd_status check_frame(const rd_ctx* h, const rd_frame* f) {
     if (!f || !f->data) return RD_E_INVALID;
@@ -158,25 +77,6 @@ rd_status check_frame(const rd_ctx* h, const rd_frame* f) {
     if (f->width > h->max_w || f->height > h->max_h) return RD_E_TOO_LARGE;
     return RD_OK;
 }
-
-rd_status upload_tables(rd_ctx* h, const rd_params& p) {
-    const size_t budget = static_cast<size_t>(h->tune.vote_lds_kb) * 1024;
-    if (h->tab_valid && same_params(h->tab_params, p) && h->tab_budget == budget) return RD_OK;
-    build_tables(p, h->tabs, budget);
-    const LevelTables& t = h->tabs;
-    RD_HIP(hipMemcpyAsync(h->d_wtab, t.wtab.data(), t.wtab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
-    RD_HIP(hipMemcpyAsync(h->d_ktab, t.ktab.data(), t.ktab.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-    RD_HIP(hipMemcpyAsync(h->d_thr, t.thr.data(), t.thr.size() * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
-    RD_HIP(hipMemcpyAsync(h->d_chunks, t.chunks.data(), t.chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                          h->stream));
-    RD_HIP(hipStreamSynchronize(h->stream));   // the host vectors may change on the next call
-    h->tab_params = p;
-    h->tab_budget = budget;
-    h->tab_valid = true;
-    return RD_OK;
-}
-
-int vote_tiles(int W, int H) { return ((W + VOTE_TILE - 1) / VOTE_TILE) * ((H + VOTE_TILE - 1) / VOTE_TILE); }
 
 // Frame descriptors of a launch; host frames are copied into the staging area.
 rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int variant, bool dense, int* total_tiles,
@@ -241,6 +141,63 @@ StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_t
     a.bin_count = h->d_bin_count;
     a.ridge_total = h->d_stats + 8;
     return a;
+}
+
+
+// Steps 1-2 on one frame: the ridges land in the context's bins.
+rd_status find_ridges(rd_ctx* h, const rd_frame* frame, const rd_params& p) {
+    const int rg = gauss_radius(p.sigma_smooth);
+    int tt = 0, tv = 0;
+    RD_TRY(setup_frames(h, frame, 1, rg, h->tune.stencil_tile, false, &tt, &tv));
+    StencilArgs sa = stencil_args(h, p, 1, tt);
+    sa.ridge_total = nullptr;
+    RD_HIP(launch_stencil(sa, frame->dtype, rg, h->tune.stencil_tile, false, h->stream));
+    return RD_OK;
+}
+
+// The binned ridges of the last single-frame launch as a list in bin order: per-bin counts
+// come back to the host, which forms the offsets, then one gather kernel copies.
+rd_status gather_ridges(rd_ctx* h, int32_t* xy, int16_t* q, float* k, int64_t capacity, int64_t* n) {
+    const FrameDesc& fd = h->h_frames[0];
+    const int64_t nbins = static_cast<int64_t>(fd.nbx) * fd.nby;
+    std::vector<uint32_t> cnt(nbins);
+    RD_HIP(hipMemcpyAsync(cnt.data(), h->d_bin_count, nbins * 4, hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    std::vector<int64_t> off(nbins);
+    int64_t tot = 0;
+    for (int64_t b = 0; b < nbins; ++b) {
+        off[b] = tot;
+        tot += cnt[b];
+    }
+    *n = tot;
+    if (tot > capacity) return RD_E_TRUNCATED;
+    if (tot == 0) return RD_OK;
+    if (!xy && !q && !k) return RD_OK;
+    RD_HIP(hipMemcpyAsync(h->d_offsets, off.data(), nbins * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+    RD_HIP(launch_gather(h->d_rxy, h->d_rq, h->d_rk, h->d_bin_count, h->d_offsets, nbins, xy, q, k, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    return RD_OK;
+}
+
+}  // namespace rd
+
+namespace {
+
+rd_status upload_tables(rd_ctx* h, const rd_params& p) {
+    const size_t budget = static_cast<size_t>(h->tune.vote_lds_kb) * 1024;
+    if (h->tab_valid && same_params(h->tab_params, p) && h->tab_budget == budget) return RD_OK;
+    build_tables(p, h->tabs, budget);
+    const LevelTables& t = h->tabs;
+    RD_HIP(hipMemcpyAsync(h->d_wtab, t.wtab.data(), t.wtab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
+    RD_HIP(hipMemcpyAsync(h->d_ktab, t.ktab.data(), t.ktab.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    RD_HIP(hipMemcpyAsync(h->d_thr, t.thr.data(), t.thr.size() * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
+    RD_HIP(hipMemcpyAsync(h->d_chunks, t.chunks.data(), t.chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));   // the host vectors may change on the next call
+    h->tab_params = p;
+    h->tab_budget = budget;
+    h->tab_valid = true;
+    return RD_OK;
 }
 
 VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles) {
@@ -585,6 +542,7 @@ void rd_destroy(rd_handle h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    soft_state_free(h->soft);
     (void)hipFree(h->d_stage);
     (void)hipFree(h->d_rxy);
     (void)hipFree(h->d_rq);
@@ -754,32 +712,8 @@ rd_status rd_stage_ridges(rd_handle h, const rd_frame* frame, const rd_params* p
     RD_TRY(rd_validate_params(params));
     RD_TRY(check_frame(h, frame));
     RD_HIP(hipSetDevice(h->device));
-    const int rg = gauss_radius(params->sigma_smooth);
-    int tt = 0, tv = 0;
-    RD_TRY(setup_frames(h, frame, 1, rg, h->tune.stencil_tile, false, &tt, &tv));
-    StencilArgs sa = stencil_args(h, *params, 1, tt);
-    sa.ridge_total = nullptr;
-    RD_HIP(launch_stencil(sa, frame->dtype, rg, h->tune.stencil_tile, false, h->stream));
-    // per-bin counts -> offsets on the host (a debug path), then one gather kernel
-    const FrameDesc& fd = h->h_frames[0];
-    const int64_t nbins = static_cast<int64_t>(fd.nbx) * fd.nby;
-    std::vector<uint32_t> cnt(nbins);
-    RD_HIP(hipMemcpyAsync(cnt.data(), h->d_bin_count, nbins * 4, hipMemcpyDeviceToHost, h->stream));
-    RD_HIP(hipStreamSynchronize(h->stream));
-    std::vector<int64_t> off(nbins);
-    int64_t tot = 0;
-    for (int64_t b = 0; b < nbins; ++b) {
-        off[b] = tot;
-        tot += cnt[b];
-    }
-    *n_ridges = tot;
-    if (tot > capacity) return RD_E_TRUNCATED;
-    if (tot == 0) return RD_OK;
-    RD_HIP(hipMemcpyAsync(h->d_offsets, off.data(), nbins * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
-    RD_HIP(launch_gather(h->d_rxy, h->d_rq, h->d_rk, h->d_bin_count, h->d_offsets, nbins, xy_dev, q_dev, k_dev,
-                         h->stream));
-    RD_HIP(hipStreamSynchronize(h->stream));
-    return RD_OK;
+    RD_TRY(find_ridges(h, frame, *params));
+    return gather_ridges(h, xy_dev, q_dev, k_dev, capacity, n_ridges);
 }
 
 rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev, int64_t n, int32_t width,

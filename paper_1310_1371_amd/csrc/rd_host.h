@@ -1,0 +1,117 @@
+// Host-side context of the ridge-directed Hough library, shared by the host sources: the
+// status macros, the cached per-level tables, the key of a captured launch sequence and the
+// context that owns every device buffer.
+#pragma once
+
+#include <cstring>
+#include <vector>
+
+#include "rd_internal.h"
+
+#define RD_HIP(call)                                   \
+    do {                                               \
+        if ((call) != hipSuccess) return RD_E_DEVICE;  \
+    } while (0)
+
+#define RD_TRY(call)                      \
+    do {                                  \
+        const rd_status st_ = (call);     \
+        if (st_ != RD_OK) return st_;     \
+    } while (0)
+
+namespace rd {
+
+// Level tables for radii r_min - 1 .. r_max + 1 (index l - (r_min - 1)).
+struct LevelTables {
+    int lbase = 0, L = 0;
+    std::vector<uint32_t> wtab;      // L x (K_MAX + 1)
+    std::vector<int32_t> ktab;       // L
+    std::vector<uint64_t> thr;       // L
+    std::vector<int32_t> chunks;     // chunk boundaries over r_min .. r_max + 1
+    size_t lds = 0;
+};
+
+inline bool same_params(const rd_params& a, const rd_params& b) {
+    return std::memcmp(&a, &b, sizeof(rd_params)) == 0;
+}
+
+// Everything a captured launch sequence bakes into its kernel arguments and grids; frame
+// pointers and sizes live in the device-side descriptor table and may change freely.
+struct GraphKey {
+    int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, nchunks = 0, blocks = 0;
+    size_t lds = 0;
+    rd_params params{};
+    bool operator==(const GraphKey& o) const {
+        return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant &&
+               total_tiles == o.total_tiles && total_vtiles == o.total_vtiles && nchunks == o.nchunks &&
+               blocks == o.blocks && lds == o.lds && same_params(params, o.params);
+    }
+};
+
+struct SoftState;                     // scratch of the differentiable path, made on first use
+void soft_state_free(SoftState* s);
+
+}  // namespace rd
+
+struct rd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cus = 0;
+    int max_w = 0, max_h = 0, max_peaks = 0, max_frames = 0;
+    int64_t max_batch_px = 0;
+    int64_t max_bins = 0;
+    // device scratch
+    void* d_stage = nullptr;            // host frames are staged here (4 bytes per pixel)
+    uint32_t* d_rxy = nullptr;          // ridge records, BIN_CAP slots per 16x16 bin
+    uint32_t* d_rq = nullptr;
+    float* d_rk = nullptr;
+    uint32_t* d_bin_count = nullptr;
+    rd::Peak* d_peaks = nullptr;        // max_peaks per frame
+    uint32_t* d_counts = nullptr;       // [0, mf) peaks per frame, [mf] bin overflow, [mf+1] vote error,
+                                        // [mf+2] vote tile queue
+    unsigned long long* d_stats = nullptr;
+    rd::FrameDesc* d_frames = nullptr;
+    uint32_t* d_wtab = nullptr;
+    int32_t* d_ktab = nullptr;
+    uint64_t* d_thr = nullptr;
+    int32_t* d_chunks = nullptr;
+    int64_t* d_offsets = nullptr;       // stage gather offsets (per bin of one frame)
+    // pinned host memory; rings and counts are written by the fit kernel through mappings
+    rd_ring* h_rings = nullptr;
+    rd_ring* dh_rings = nullptr;
+    uint32_t* h_counts = nullptr;
+    uint32_t* dh_counts = nullptr;
+    rd::FrameDesc* h_frames = nullptr;
+    uint64_t* h_stats = nullptr;
+    // kernel timing
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double t_ms[3] = {0, 0, 0};
+    int64_t t_n[3] = {0, 0, 0};
+    // tuning and the cached level tables
+    rd_tuning tune{0, 52, 1};
+    rd_params tab_params{};
+    size_t tab_budget = 0;
+    bool tab_valid = false;
+    rd::LevelTables tabs;
+    // captured launch sequence
+    hipGraphExec_t gexec = nullptr;
+    rd::GraphKey gkey;
+    int64_t last_stats[6] = {0, 0, 0, 0, 0, 0};
+    // differentiable path
+    rd::SoftState* soft = nullptr;
+};
+
+namespace rd {
+
+// Shared host helpers (defined with the plain entry points).
+int gauss_radius(float sigma);
+int vote_tiles(int W, int H);
+rd_status check_frame(const rd_ctx* h, const rd_frame* f);
+rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int variant, bool dense, int* total_tiles,
+                       int* total_vtiles);
+StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_tiles);
+rd_status find_ridges(rd_ctx* h, const rd_frame* frame, const rd_params& p);
+rd_status gather_ridges(rd_ctx* h, int32_t* xy, int16_t* q, float* k, int64_t capacity, int64_t* n);
+
+}  // namespace rd

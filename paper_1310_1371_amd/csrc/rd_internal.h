@@ -50,6 +50,7 @@ struct StencilArgs {
     uint32_t* bin_count;     // ridges per bin
     float* k_dense;          // dense outputs (stage mode, single frame)
     int16_t* q_dense;
+    double* hess_dense;      // dense mode: Ixx, Iyy, Ixy planes [3][H][W] (may be null)
     unsigned long long* ridge_total;   // statistics: ridges found (may be null)
 };
 
@@ -123,5 +124,103 @@ hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s);
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* rk, const uint32_t* bin_count,
                          const int64_t* offsets, int64_t nbins, int32_t* xy, int16_t* q, float* k, hipStream_t s);
+
+// ---- differentiable path (soft accumulator, adjoints, ring-profile fit)
+
+constexpr int SOFT_TILE = 32;     // accumulator tile side owned by one workgroup
+constexpr int SOFT_LEVELS = 8;    // accumulator levels per workgroup (32 KB of LDS)
+
+// Ridges of a soft launch binned by 16x16 pixel bins, with their splat geometry.
+struct SoftBinArgs {
+    const int32_t* xy;       // [n][2] ridge pixels
+    const double* hess;      // [n][3] Ixx, Iyy, Ixy at the ridge pixels
+    int64_t n;
+    int32_t W, H, nbx;
+    uint32_t* sxy;           // per slot: x | y << 16
+    double* sux;             // per slot: X_- (continuous)
+    double* suy;
+    float* sw;               // per slot: w = -k_-
+    uint32_t* bin_count;
+    uint32_t* flags;         // bit 0: a bin overflowed, bit 1: a ridge off the frame
+};
+
+struct SoftFwdArgs {
+    const uint32_t* sxy;
+    const double* sux;
+    const double* suy;
+    const float* sw;
+    const uint32_t* bin_count;
+    int32_t W, H, nbx, nby;
+    int32_t r_lo, L;         // levels r_lo .. r_lo + L - 1
+    float* acc;              // [L][H][W]
+};
+
+struct SoftBwdArgs {
+    const int32_t* xy;
+    const double* hess;
+    int64_t n;
+    int32_t W, H, r_lo, L;
+    const float* grad_acc;   // [L][H][W]
+    double* grad_hess;       // [n][3]
+    uint32_t* n_iso;         // near-isotropic ridges whose X_- term was dropped
+};
+
+// One pass of a transposed 1D correlation with reflect-101 fold-back along x (dir 0) or
+// y (dir 1).  sum = 0: out[c] = scale T_c(in[c]) for each component; sum = 1:
+// out[0] = scale sum_c T_c(in[c]); accumulate adds into out instead of overwriting.
+constexpr int ADJ_TAPS = 2 * RG_MAX + 1;
+struct AdjPassArgs {
+    const float* in[3];
+    float* out[3];
+    double taps[3][ADJ_TAPS];
+    int32_t ncomp, R, W, H, sum, accumulate;
+    double scale;
+};
+
+struct ScatterArgs {
+    const int32_t* xy;
+    const double* grad_hess;
+    int64_t n;
+    int32_t W, H;
+    float* planes;           // [3][H][W], zeroed before
+};
+
+// A frame of a ring-profile launch.
+struct RingFrame {
+    const void* img;
+    int64_t pitch;           // bytes
+    int32_t W, H, dtype, pad;
+};
+
+constexpr int RING_FRAMES_MAX = 64;   // frames of one ring-profile launch (kernel arguments)
+struct RingArgs {
+    RingFrame frames[RING_FRAMES_MAX];
+    int32_t nframes;
+    const int32_t* frame_of; // [m] frame of each ring (null: frame 0); rings of other indices are skipped
+    int64_t m;
+    const double* theta;     // [m][3] cx, cy, r
+    const double* theta0;    // [m][3] ring that fixes the window
+    double s, halfwidth;     // profile sigma, window half-width 3 s + 2
+    double* loss;            // [m]
+    double* ab;              // [m][2] A, B (may be null)
+    const double* grad_loss; // backward: [m] upstream gradient
+    float* grad_img;         // backward: [H][W] of frame 0, added into (may be null)
+    double* grad_theta;      // backward: [m][3]
+    int32_t iters;           // refinement steps
+    double lam0, lam_down, lam_up;
+    double* theta_out;       // refinement result [m][3]
+};
+
+hipError_t launch_hess_gather(const double* planes, int W, int H, const int32_t* xy, int64_t n, double* hess,
+                              hipStream_t s);
+hipError_t launch_soft_bin(const SoftBinArgs& a, hipStream_t s);
+hipError_t launch_soft_forward(const SoftFwdArgs& a, hipStream_t s);
+hipError_t launch_soft_backward(const SoftBwdArgs& a, hipStream_t s);
+hipError_t launch_scatter_grad_hess(const ScatterArgs& a, hipStream_t s);
+hipError_t launch_adj_pass(const AdjPassArgs& a, int dir, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_fit_loss(const RingArgs& a, bool backward, hipStream_t s);
+hipError_t launch_refine(const RingArgs& a, hipStream_t s);
 
 }  // namespace rd

@@ -10,7 +10,7 @@
 //   and wave-ballot compaction of the ridge pixels into their 16x16 bins.
 // Only the input is read from HBM and only the ridges are written, so nothing of the
 // smoothed image, the Hessian or k_- ever goes to memory (except in the dense stage mode,
-// which writes k_- and q for parity checks).
+// which writes k_- and q, and optionally the Hessian planes, of a single frame).
 //
 // The filters run in fp64: the Hessian is a small difference of large smoothed values
 // (e.g. a 12-bit frame with a 600-count background and curvatures of order 1 count/px^2),
@@ -210,6 +210,15 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
                     const double k = tr - d;
                     sK[r * KW + c] = k;
                     sQ[r * KW + c] = (DENSE || k < kthr) ? direction_code(h, ixy, d) : 0u;
+                    if (DENSE && a.hess_dense && r >= 1 && r <= TH && c >= 1 && c <= TW) {
+                        const int x = x0 - 1 + c, y = y0 - 1 + r;
+                        if (x < W && y < H) {
+                            const int64_t g = (int64_t)y * W + x, plane = (int64_t)W * H;
+                            a.hess_dense[g] = ixx;
+                            a.hess_dense[plane + g] = iyy;
+                            a.hess_dense[2 * plane + g] = ixy;
+                        }
+                    }
                 }
             }
         }
@@ -223,10 +232,12 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
                 if (x < W && y < H) {
                     const int o = (py + 1) * KW + px + 1;
                     const int64_t g = (int64_t)y * W + x;
-                    a.k_dense[g] = static_cast<float>(sK[o]);
-                    const uint32_t q = sQ[o];
-                    a.q_dense[2 * g] = static_cast<int16_t>(q & 0xffffu);
-                    a.q_dense[2 * g + 1] = static_cast<int16_t>(q >> 16);
+                    if (a.k_dense) a.k_dense[g] = static_cast<float>(sK[o]);
+                    if (a.q_dense) {
+                        const uint32_t q = sQ[o];
+                        a.q_dense[2 * g] = static_cast<int16_t>(q & 0xffffu);
+                        a.q_dense[2 * g + 1] = static_cast<int16_t>(q >> 16);
+                    }
                 }
             }
         } else {

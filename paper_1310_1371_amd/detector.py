@@ -221,6 +221,125 @@ class Detector:
         return xy, q
 
 
+    # -------------------------------------------------------------------- differentiable path
+    def _dev(self):
+        return f"cuda:{self.device}"
+
+    def soft_ridges(self, frame, params: dict, capacity: int | None = None):
+        """Ridge set (int32 [n, 2]) and the Hessian (Ixx, Iyy, Ixy) at each ridge (float64 [n, 3])."""
+        fr = _frame_struct(frame)
+        if capacity is None:
+            capacity = fr.width * fr.height
+        xy = torch.empty((capacity, 2), dtype=torch.int32, device=self._dev())
+        hess = torch.empty((capacity, 3), dtype=torch.float64, device=self._dev())
+        p = N.make_params(params)
+        n = ctypes.c_int64()
+        N.check(self._lib.rd_soft_ridges(self._h, ctypes.byref(fr), ctypes.byref(p), xy.data_ptr(), hess.data_ptr(),
+                                         capacity, ctypes.byref(n)), "rd_soft_ridges")
+        return xy[:n.value], hess[:n.value]
+
+    def _soft_inputs(self, xy, hess):
+        xy = torch.as_tensor(xy).to(device=self._dev(), dtype=torch.int32).contiguous().reshape(-1, 2)
+        hess = torch.as_tensor(hess).to(device=self._dev(), dtype=torch.float64).contiguous().reshape(-1, 3)
+        if xy.shape[0] != hess.shape[0]:
+            raise ValueError("xy and hess must have the same length")
+        return xy, hess
+
+    def soft_forward(self, xy, hess, width: int, height: int, params: dict) -> torch.Tensor:
+        """Soft accumulator, float32 [L, H, W] with L = r_max - r_min + 3."""
+        xy, hess = self._soft_inputs(xy, hess)
+        L = int(params["r_max"]) - int(params["r_min"]) + 3
+        acc = torch.empty((L, height, width), dtype=torch.float32, device=self._dev())
+        p = N.make_params(params)
+        N.check(self._lib.rd_soft_forward(self._h, xy.data_ptr(), hess.data_ptr(), xy.shape[0], width, height,
+                                          ctypes.byref(p), acc.data_ptr()), "rd_soft_forward")
+        return acc
+
+    def soft_backward(self, xy, hess, width: int, height: int, params: dict, grad_acc: torch.Tensor,
+                      count_isotropic: bool = False):
+        """d/d(Ixx, Iyy, Ixy) per ridge (float64 [n, 3]) from dL/dA~; with count_isotropic also the
+        number of near-isotropic ridges whose eigenvector term was dropped."""
+        xy, hess = self._soft_inputs(xy, hess)
+        L = int(params["r_max"]) - int(params["r_min"]) + 3
+        g = grad_acc.to(device=self._dev(), dtype=torch.float32).contiguous()
+        if tuple(g.shape) != (L, height, width):
+            raise ValueError(f"grad_acc must have shape {(L, height, width)}")
+        out = torch.empty((xy.shape[0], 3), dtype=torch.float64, device=self._dev())
+        p = N.make_params(params)
+        n_iso = ctypes.c_int64()
+        N.check(self._lib.rd_soft_backward(self._h, xy.data_ptr(), hess.data_ptr(), xy.shape[0], width, height,
+                                           ctypes.byref(p), g.data_ptr(), out.data_ptr(),
+                                           ctypes.byref(n_iso) if count_isotropic else None),
+                "rd_soft_backward")
+        return (out, n_iso.value) if count_isotropic else out
+
+    def hessian_backward(self, xy, grad_hess, width: int, height: int, params: dict,
+                         grad_img: torch.Tensor | None = None) -> torch.Tensor:
+        """Adds the image gradient of per-ridge Hessian gradients into grad_img (float32 [H, W],
+        zeros if None) and returns it."""
+        xy, grad_hess = self._soft_inputs(xy, grad_hess)
+        if grad_img is None:
+            grad_img = torch.zeros((height, width), dtype=torch.float32, device=self._dev())
+        if grad_img.dtype != torch.float32 or not grad_img.is_contiguous() or tuple(grad_img.shape) != (height, width):
+            raise ValueError("grad_img must be a contiguous float32 [H, W] tensor")
+        p = N.make_params(params)
+        N.check(self._lib.rd_hessian_backward(self._h, xy.data_ptr(), grad_hess.data_ptr(), xy.shape[0], width,
+                                              height, ctypes.byref(p), grad_img.data_ptr()), "rd_hessian_backward")
+        return grad_img
+
+    def _thetas(self, theta):
+        return torch.as_tensor(theta).to(device=self._dev(), dtype=torch.float64).contiguous().reshape(-1, 3)
+
+    def fit_loss(self, frame, theta, theta0, s: float):
+        """Ring fit loss per ring (float64 [m]) and (A, B) per ring (float64 [m, 2])."""
+        fr = _frame_struct(frame)
+        theta, theta0 = self._thetas(theta), self._thetas(theta0)
+        m = theta.shape[0]
+        loss = torch.empty((m,), dtype=torch.float64, device=self._dev())
+        ab = torch.empty((m, 2), dtype=torch.float64, device=self._dev())
+        N.check(self._lib.rd_fit_loss(self._h, ctypes.byref(fr), theta.data_ptr(), theta0.data_ptr(), m, float(s),
+                                      loss.data_ptr(), ab.data_ptr()), "rd_fit_loss")
+        return loss, ab
+
+    def fit_loss_backward(self, frame, theta, theta0, s: float, grad_loss, grad_img: torch.Tensor | None = None):
+        """(grad_img with d/dI added, or None; d/dtheta float64 [m, 3]) of sum_j grad_loss[j] L_j."""
+        fr = _frame_struct(frame)
+        theta, theta0 = self._thetas(theta), self._thetas(theta0)
+        m = theta.shape[0]
+        gl = torch.as_tensor(grad_loss).to(device=self._dev(), dtype=torch.float64).contiguous().reshape(-1)
+        if gl.shape[0] != m:
+            raise ValueError("grad_loss must have one entry per ring")
+        if grad_img is not None and (grad_img.dtype != torch.float32 or not grad_img.is_contiguous()
+                                     or tuple(grad_img.shape) != (fr.height, fr.width)):
+            raise ValueError("grad_img must be a contiguous float32 [H, W] tensor")
+        gt = torch.empty((m, 3), dtype=torch.float64, device=self._dev())
+        N.check(self._lib.rd_fit_loss_backward(self._h, ctypes.byref(fr), theta.data_ptr(), theta0.data_ptr(), m,
+                                               float(s), gl.data_ptr(),
+                                               grad_img.data_ptr() if grad_img is not None else None,
+                                               gt.data_ptr()), "rd_fit_loss_backward")
+        return grad_img, gt
+
+    def refine(self, frames, theta0, s: float, iters: int = 20, frame_of=None):
+        """Levenberg-Marquardt refinement: (theta float64 [m, 3], loss float64 [m]).  frames is one
+        device frame or a list of up to 64; frame_of gives each ring's frame index."""
+        if not isinstance(frames, (list, tuple)):
+            frames = [frames]
+        arr = (N.RdFrame * len(frames))(*[_frame_struct(f) for f in frames])
+        theta0 = self._thetas(theta0)
+        m = theta0.shape[0]
+        fo = None
+        if frame_of is not None:
+            fo = torch.as_tensor(frame_of).to(device=self._dev(), dtype=torch.int32).contiguous().reshape(-1)
+            if fo.shape[0] != m:
+                raise ValueError("frame_of must have one entry per ring")
+        theta = torch.empty((m, 3), dtype=torch.float64, device=self._dev())
+        loss = torch.empty((m,), dtype=torch.float64, device=self._dev())
+        N.check(self._lib.rd_refine(self._h, arr, len(frames), fo.data_ptr() if fo is not None else None,
+                                    theta0.data_ptr(), m, float(s), int(iters), theta.data_ptr(), loss.data_ptr()),
+                "rd_refine")
+        return theta, loss
+
+
 def validate_params(params: dict) -> int:
     """Host-only parameter check (no GPU needed); returns an rd_status code."""
     p = N.make_params(params)
