@@ -7,9 +7,17 @@
 // "Directed ridge detection & votes collection"); this profile fit refines those circles on
 // the image itself.
 //
-// One workgroup per ring.  Every pass walks the window's bounding box; membership is decided
-// in fp64 with separately rounded operations, so each pixel is in or out exactly as a float64
-// reference decides.  All sums are fp64.
+// One workgroup per ring.  The window's members are found once, by walking its bounding box
+// with membership decided in fp64 with separately rounded operations (each pixel is in or out
+// exactly as a float64 reference decides), and compacted into LDS with their intensities;
+// every later pass reads the LDS list.  Windows larger than the list fall back to walking the
+// box on every pass.  All sums are fp64.
+//
+// Refinement pass: one sweep per LM step.  With d = dg/dtheta, the sweep accumulates
+//   sum g, sum g^2, sum I g, sum d d^T, sum d I, sum d, sum d g
+// (n, sum I, sum I^2 once per ring).  From these, in closed form: (A, B); the loss at the
+// optimum L = sum I^2 - A sum I g - B sum I (the residual is orthogonal to 1 and g);
+// J^T J = A^2 sum d d^T and -J^T e = A (sum d I - B sum d - A sum d g) for J = -A d.
 #include "rd_internal.h"
 
 namespace rd {
@@ -17,6 +25,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NW = NT / 64;
+constexpr int WCAP = 6144;   // window members held in LDS (8 bytes each)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -79,30 +88,110 @@ __device__ __forceinline__ bool in_window(const Window& w, int x, int y) {
     return fabs(__dsub_rn(rho, w.r0)) <= w.m;
 }
 
-__device__ __forceinline__ double pixel(const RingFrame& f, int x, int y) {
+__device__ __forceinline__ float pixel(const RingFrame& f, int x, int y) {
     const char* row = static_cast<const char*>(f.img) + static_cast<int64_t>(y) * f.pitch;
-    return f.dtype == RD_U16 ? static_cast<double>(reinterpret_cast<const uint16_t*>(row)[x])
-                             : static_cast<double>(reinterpret_cast<const float*>(row)[x]);
+    return f.dtype == RD_U16 ? static_cast<float>(reinterpret_cast<const uint16_t*>(row)[x])
+                             : reinterpret_cast<const float*>(row)[x];
+}
+
+// The window's members: either compacted in LDS (listed) or found again on every pass.
+struct Members {
+    const uint32_t* pos;   // (x - x0) | (y - y0) << 16
+    const float* val;
+    int n;
+    bool listed;
+};
+
+__device__ Members build_members(const RingFrame& f, const Window& w, uint32_t* sPos, float* sVal,
+                                 uint32_t* sCnt) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
+    int base = 0;
+    bool listed = true;
+    for (int64_t c0 = 0; c0 < nbox; c0 += NT) {
+        const int64_t i = c0 + threadIdx.x;
+        int x = 0, y = 0;
+        bool mem = false;
+        if (i < nbox) {
+            y = w.y0 + static_cast<int>(i / w.bw);
+            x = w.x0 + static_cast<int>(i % w.bw);
+            mem = in_window(w, x, y);
+        }
+        const uint64_t ball = __ballot(mem);
+        if (lane == 0) sCnt[wave] = static_cast<uint32_t>(__popcll(ball));
+        __syncthreads();
+        int off = base, tot = 0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            off += v < wave ? static_cast<int>(sCnt[v]) : 0;
+            tot += static_cast<int>(sCnt[v]);
+        }
+        __syncthreads();
+        if (mem) {
+            const int slot = off + __popcll(ball & ((1ull << lane) - 1ull));
+            if (slot < WCAP) {
+                sPos[slot] = static_cast<uint32_t>(x - w.x0) | (static_cast<uint32_t>(y - w.y0) << 16);
+                sVal[slot] = pixel(f, x, y);
+            }
+        }
+        base += tot;
+        if (base > WCAP) {
+            listed = false;
+            break;
+        }
+    }
+    __syncthreads();
+    Members m;
+    m.pos = sPos;
+    m.val = sVal;
+    m.n = listed ? base : 0;
+    m.listed = listed;
+    return m;
+}
+
+// Calls fn(x, y, I) for every member handled by this thread.
+template <class F>
+__device__ __forceinline__ void for_members(const RingFrame& f, const Window& w, const Members& M, F&& fn) {
+    if (M.listed) {
+        for (int i = threadIdx.x; i < M.n; i += NT) {
+            const uint32_t p = M.pos[i];
+            fn(w.x0 + static_cast<int>(p & 0xffffu), w.y0 + static_cast<int>(p >> 16), static_cast<double>(M.val[i]));
+        }
+    } else {
+        const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
+        for (int64_t i = threadIdx.x; i < nbox; i += NT) {
+            const int y = w.y0 + static_cast<int>(i / w.bw), x = w.x0 + static_cast<int>(i % w.bw);
+            if (in_window(w, x, y)) fn(x, y, static_cast<double>(pixel(f, x, y)));
+        }
+    }
 }
 
 struct Prof {
     double g, rho, dgdrho;
 };
 
-__device__ __forceinline__ Prof profile(double cx, double cy, double r, double inv2s2, double invs2, int x, int y) {
+__device__ __forceinline__ Prof profile(const double* th, double inv2s2, double invs2, int x, int y) {
     Prof p;
-    const double dx = x - cx, dy = y - cy;
+    const double dx = x - th[0], dy = y - th[1];
     p.rho = sqrt(dx * dx + dy * dy);
-    const double t = p.rho - r;
+    const double t = p.rho - th[2];
     p.g = exp(-(t * t) * inv2s2);
     p.dgdrho = -p.g * t * invs2;
     return p;
 }
 
-// Closed-form (A, B) from the sums n, Sg, Sgg, SI, SIg (Cramer's rule on the 2x2 normal
+// dg/d(cx, cy, r); at rho = 0 the centre derivatives are taken as 0.
+__device__ __forceinline__ void profile_grad(const Prof& p, const double* th, int x, int y, double d[3]) {
+    const double safe = p.rho > 0.0 ? p.rho : 1.0;
+    d[0] = p.dgdrho * (-(x - th[0]) / safe);
+    d[1] = p.dgdrho * (-(y - th[1]) / safe);
+    d[2] = -p.dgdrho;
+}
+
+// Closed-form (A, B) from n, sum g, sum g^2, sum I, sum I g (Cramer's rule on the 2x2 normal
 // equations); an empty window gives (0, 0), a singular system A = 0, B = mean I.
-__device__ __forceinline__ void solve_ab(const double* s, double& A, double& B) {
-    const double n = s[0], Sg = s[1], Sgg = s[2], SI = s[3], SIg = s[4];
+__device__ __forceinline__ void solve_ab(double n, double Sg, double Sgg, double SI, double SIg, double& A,
+                                         double& B) {
     if (n == 0.0) {
         A = 0.0;
         B = 0.0;
@@ -118,43 +207,27 @@ __device__ __forceinline__ void solve_ab(const double* s, double& A, double& B) 
     B = (Sgg * SI - Sg * SIg) / det;
 }
 
-// (A, B) at ring th; returns nothing, fills A, B.
-__device__ void fit_ab(const RingFrame& f, const Window& w, const double* th, double inv2s2, double invs2,
-                       double* sred, double& A, double& B) {
+// (A, B) at ring th: sums n, g, g^2, I, I g.
+__device__ void fit_ab(const RingFrame& f, const Window& w, const Members& M, const double* th, double inv2s2,
+                       double invs2, double* sred, double& A, double& B) {
     double s[5] = {0, 0, 0, 0, 0};
-    const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
-    for (int64_t i = threadIdx.x; i < nbox; i += NT) {
-        const int y = w.y0 + static_cast<int>(i / w.bw), x = w.x0 + static_cast<int>(i % w.bw);
-        if (!in_window(w, x, y)) continue;
-        const double I = pixel(f, x, y);
-        const Prof p = profile(th[0], th[1], th[2], inv2s2, invs2, x, y);
+    for_members(f, w, M, [&](int x, int y, double I) {
+        const Prof p = profile(th, inv2s2, invs2, x, y);
         s[0] += 1.0;
         s[1] += p.g;
         s[2] += p.g * p.g;
         s[3] += I;
         s[4] += I * p.g;
-    }
+    });
     block_sum<5>(s, sred);
-    solve_ab(s, A, B);
-}
-
-__device__ double residual_loss(const RingFrame& f, const Window& w, const double* th, double A, double B,
-                                double inv2s2, double invs2, double* sred) {
-    double s[1] = {0.0};
-    const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
-    for (int64_t i = threadIdx.x; i < nbox; i += NT) {
-        const int y = w.y0 + static_cast<int>(i / w.bw), x = w.x0 + static_cast<int>(i % w.bw);
-        if (!in_window(w, x, y)) continue;
-        const Prof p = profile(th[0], th[1], th[2], inv2s2, invs2, x, y);
-        const double e = pixel(f, x, y) - B - A * p.g;
-        s[0] += e * e;
-    }
-    block_sum<1>(s, sred);
-    return s[0];
+    solve_ab(s[0], s[1], s[2], s[3], s[4], A, B);
 }
 
 __global__ __launch_bounds__(NT) void k_fit_loss(RingArgs a, int backward) {
-    __shared__ double sred[NW * 8];
+    __shared__ uint32_t sPos[WCAP];
+    __shared__ float sVal[WCAP];
+    __shared__ double sred[NW * 5];
+    __shared__ uint32_t sCnt[NW];
     const double inv2s2 = 1.0 / (2.0 * a.s * a.s), invs2 = 1.0 / (a.s * a.s);
     for (int64_t j = blockIdx.x; j < a.m; j += gridDim.x) {
         const int fi = a.frame_of ? a.frame_of[j] : 0;
@@ -171,13 +244,19 @@ __global__ __launch_bounds__(NT) void k_fit_loss(RingArgs a, int backward) {
         }
         const RingFrame f = a.frames[fi];
         const Window w = make_window(a.theta0 + 3 * j, a.halfwidth, f.W, f.H);
+        const Members M = build_members(f, w, sPos, sVal, sCnt);
         const double th[3] = {a.theta[3 * j], a.theta[3 * j + 1], a.theta[3 * j + 2]};
         double A, B;
-        fit_ab(f, w, th, inv2s2, invs2, sred, A, B);
+        fit_ab(f, w, M, th, inv2s2, invs2, sred, A, B);
         if (!backward) {
-            const double L = residual_loss(f, w, th, A, B, inv2s2, invs2, sred);
+            double s[1] = {0.0};
+            for_members(f, w, M, [&](int x, int y, double I) {
+                const double e = I - B - A * profile(th, inv2s2, invs2, x, y).g;
+                s[0] += e * e;
+            });
+            block_sum<1>(s, sred);
             if (threadIdx.x == 0) {
-                a.loss[j] = L;
+                a.loss[j] = s[0];
                 if (a.ab) {
                     a.ab[2 * j] = A;
                     a.ab[2 * j + 1] = B;
@@ -188,19 +267,17 @@ __global__ __launch_bounds__(NT) void k_fit_loss(RingArgs a, int backward) {
         // dL/dI = 2 e on the window; dL/dtheta = sum -2 A e dg/dtheta ((A, B) at their optimum)
         const double gl = a.grad_loss[j];
         double s[3] = {0, 0, 0};
-        const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
-        for (int64_t i = threadIdx.x; i < nbox; i += NT) {
-            const int y = w.y0 + static_cast<int>(i / w.bw), x = w.x0 + static_cast<int>(i % w.bw);
-            if (!in_window(w, x, y)) continue;
-            const Prof p = profile(th[0], th[1], th[2], inv2s2, invs2, x, y);
-            const double e = pixel(f, x, y) - B - A * p.g;
+        for_members(f, w, M, [&](int x, int y, double I) {
+            const Prof p = profile(th, inv2s2, invs2, x, y);
+            const double e = I - B - A * p.g;
             if (a.grad_img) atomicAdd(&a.grad_img[static_cast<int64_t>(y) * f.W + x], static_cast<float>(gl * 2.0 * e));
-            const double safe = p.rho > 0.0 ? p.rho : 1.0;
-            const double c = -2.0 * A * e * p.dgdrho;
-            s[0] += c * (-(x - th[0]) / safe);
-            s[1] += c * (-(y - th[1]) / safe);
-            s[2] -= c;
-        }
+            double d[3];
+            profile_grad(p, th, x, y, d);
+            const double c = -2.0 * A * e;
+            s[0] += c * d[0];
+            s[1] += c * d[1];
+            s[2] += c * d[2];
+        });
         block_sum<3>(s, sred);
         if (threadIdx.x == 0) {
             a.grad_theta[3 * j] = gl * s[0];
@@ -242,8 +319,56 @@ __device__ bool solve3(double M[3][3], double b[3], double d[3]) {
     return true;
 }
 
+// State of an LM step at one ring position, from one sweep.
+struct LmPoint {
+    double A, B, L;
+    double JtJ[6];   // xx, xy, xr, yy, yr, rr
+    double mJte[3];  // -J^T e
+};
+
+__device__ LmPoint lm_point(const RingFrame& f, const Window& w, const Members& M, const double* th, double n,
+                            double SI, double SII, double inv2s2, double invs2, double* sred) {
+    // sums: g, g^2, I g, d d^T (6), d I (3), d (3), d g (3)
+    double s[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) s[k] = 0.0;
+    for_members(f, w, M, [&](int x, int y, double I) {
+        const Prof p = profile(th, inv2s2, invs2, x, y);
+        double d[3];
+        profile_grad(p, th, x, y, d);
+        s[0] += p.g;
+        s[1] += p.g * p.g;
+        s[2] += I * p.g;
+        s[3] += d[0] * d[0];
+        s[4] += d[0] * d[1];
+        s[5] += d[0] * d[2];
+        s[6] += d[1] * d[1];
+        s[7] += d[1] * d[2];
+        s[8] += d[2] * d[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s[9 + k] += d[k] * I;
+            s[12 + k] += d[k];
+            s[15 + k] += d[k] * p.g;
+        }
+    });
+    block_sum<18>(s, sred);
+    LmPoint q;
+    solve_ab(n, s[0], s[1], SI, s[2], q.A, q.B);
+    q.L = SII - q.A * s[2] - q.B * SI;
+    const double A2 = q.A * q.A;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q.JtJ[k] = A2 * s[3 + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q.mJte[k] = q.A * (s[9 + k] - q.B * s[12 + k] - q.A * s[15 + k]);
+    return q;
+}
+
 __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
-    __shared__ double sred[NW * 9];
+    __shared__ uint32_t sPos[WCAP];
+    __shared__ float sVal[WCAP];
+    __shared__ double sred[NW * 18];
+    __shared__ uint32_t sCnt[NW];
     const double inv2s2 = 1.0 / (2.0 * a.s * a.s), invs2 = 1.0 / (a.s * a.s);
     for (int64_t j = blockIdx.x; j < a.m; j += gridDim.x) {
         const int fi = a.frame_of ? a.frame_of[j] : 0;
@@ -256,56 +381,36 @@ __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
         }
         const RingFrame f = a.frames[fi];
         const Window w = make_window(a.theta0 + 3 * j, a.halfwidth, f.W, f.H);
+        const Members M = build_members(f, w, sPos, sVal, sCnt);
+        double c[3] = {0, 0, 0};   // n, sum I, sum I^2 over the fixed window
+        for_members(f, w, M, [&](int, int, double I) {
+            c[0] += 1.0;
+            c[1] += I;
+            c[2] += I * I;
+        });
+        block_sum<3>(c, sred);
         double th[3] = {a.theta0[3 * j], a.theta0[3 * j + 1], a.theta0[3 * j + 2]};
         double lam = a.lam0;
-        double A, B;
-        fit_ab(f, w, th, inv2s2, invs2, sred, A, B);
-        double loss = residual_loss(f, w, th, A, B, inv2s2, invs2, sred);
-        const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
+        LmPoint cur = lm_point(f, w, M, th, c[0], c[1], c[2], inv2s2, invs2, sred);
         for (int it = 0; it < a.iters; ++it) {
-            // J = -A dg/dtheta and e at the current ring: sums of J^T J (6) and J^T e (3)
-            double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (int64_t i = threadIdx.x; i < nbox; i += NT) {
-                const int y = w.y0 + static_cast<int>(i / w.bw), x = w.x0 + static_cast<int>(i % w.bw);
-                if (!in_window(w, x, y)) continue;
-                const Prof p = profile(th[0], th[1], th[2], inv2s2, invs2, x, y);
-                const double e = pixel(f, x, y) - B - A * p.g;
-                const double safe = p.rho > 0.0 ? p.rho : 1.0;
-                const double j0 = -A * p.dgdrho * (-(x - th[0]) / safe);
-                const double j1 = -A * p.dgdrho * (-(y - th[1]) / safe);
-                const double j2 = -A * -p.dgdrho;
-                s[0] += j0 * j0;
-                s[1] += j0 * j1;
-                s[2] += j0 * j2;
-                s[3] += j1 * j1;
-                s[4] += j1 * j2;
-                s[5] += j2 * j2;
-                s[6] += j0 * e;
-                s[7] += j1 * e;
-                s[8] += j2 * e;
-            }
-            block_sum<9>(s, sred);
             // (J^T J + lam diag(J^T J)) d = -J^T e, solved redundantly by every thread
-            double M[3][3] = {{s[0] + lam * s[0], s[1], s[2]},
-                              {s[1], s[3] + lam * s[3], s[4]},
-                              {s[2], s[4], s[5] + lam * s[5]}};
-            double b[3] = {-s[6], -s[7], -s[8]};
+            const double* J = cur.JtJ;
+            double Mx[3][3] = {{J[0] + lam * J[0], J[1], J[2]},
+                               {J[1], J[3] + lam * J[3], J[4]},
+                               {J[2], J[4], J[5] + lam * J[5]}};
+            double b[3] = {cur.mJte[0], cur.mJte[1], cur.mJte[2]};
             double d[3] = {0, 0, 0};
-            if (!solve3(M, b, d)) {
+            if (!solve3(Mx, b, d)) {
                 lam *= a.lam_up;
                 continue;
             }
             const double cand[3] = {th[0] + d[0], th[1] + d[1], th[2] + d[2]};
-            double A2, B2;
-            fit_ab(f, w, cand, inv2s2, invs2, sred, A2, B2);
-            const double l2 = residual_loss(f, w, cand, A2, B2, inv2s2, invs2, sred);
-            if (l2 < loss) {
+            const LmPoint nxt = lm_point(f, w, M, cand, c[0], c[1], c[2], inv2s2, invs2, sred);
+            if (nxt.L < cur.L) {
                 th[0] = cand[0];
                 th[1] = cand[1];
                 th[2] = cand[2];
-                loss = l2;
-                A = A2;
-                B = B2;
+                cur = nxt;
                 lam *= a.lam_down;
             } else {
                 lam *= a.lam_up;
@@ -315,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
             a.theta_out[3 * j] = th[0];
             a.theta_out[3 * j + 1] = th[1];
             a.theta_out[3 * j + 2] = th[2];
-            if (a.loss) a.loss[j] = loss;
+            if (a.loss) a.loss[j] = cur.L;
         }
     }
 }

@@ -274,3 +274,21 @@ def test_autograd_check_objective(det):
     assert abs(total.item() - ref_L) <= 1e-5 * abs(ref_L) + 1e-4
     _close(theta.grad.cpu().numpy(), ref_dth, 1e-8, 1e-10, "dL/dtheta")
     _close(image.grad.cpu().numpy(), ref_dI, 1e-4, 1e-5, "dL/dI")
+
+
+def test_large_window_streams_from_the_frame(det):
+    """A ring whose window holds more pixels than the per-ring list (r ~ 100 px, about 8200
+    pixels) is fitted by walking its bounding box on every pass: same results."""
+    theta = np.array([128.4, 127.7, 100.3])
+    rng = np.random.default_rng(5)
+    img = (S.render_ring(256, 256, theta, 1.5, 1.0, 0.2) + rng.normal(0, 0.05, (256, 256))).astype(np.float32)
+    th0 = theta + np.array([[0.5, -0.4, 0.6]])
+    assert len(S.ring_window(th0[0], 1.5, 256, 256)[0]) > 6144
+    say("[fit] large window")
+    t = torch.from_numpy(img).cuda()
+    th, loss = det.refine(t, th0, 1.5, iters=20)
+    ref_th, ref_l = S.refine(img, th0[0], 1.5, iters=20)
+    assert np.abs(th.cpu().numpy()[0] - ref_th).max() <= 1e-6
+    assert abs(loss[0].item() - ref_l) <= 1e-9 * ref_l
+    l2, ab = det.fit_loss(t, th0 + 0.2, th0, 1.5)
+    assert abs(l2[0].item() - S.fit_loss(img, th0[0] + 0.2, th0[0], 1.5)[0]) <= 1e-10 * l2[0].item()
