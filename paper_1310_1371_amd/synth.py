@@ -209,21 +209,32 @@ def _c1_geometry_counts(rng, W, H, n_rings, r_lo=10.0, r_hi=30.0, max_attempts=3
     return img, cx, cy, R, s, A
 
 
+def config3_plan(seed: int = 2, n_frames: int = 64) -> list[tuple]:
+    """(width, height, rings asked for, frame seed) of each frame of the uneven batch."""
+    ss = np.random.SeedSequence(seed)
+    top = np.random.Generator(np.random.PCG64(ss))
+    children = ss.spawn(n_frames)
+    plan = []
+    for i in range(n_frames):
+        W, H = BATCH_SIZES[int(top.integers(0, len(BATCH_SIZES)))]
+        n_rings = int(top.integers(50, 801))
+        plan.append((W, H, n_rings, children[i]))
+    return plan
+
+
+def config3_frame(item, seed: int = 2, max_attempts: int = 300_000) -> Frame:
+    """One frame of the uneven batch from its plan entry (frames can be made in parallel)."""
+    W, H, n_rings, child = item
+    rng = np.random.Generator(np.random.PCG64(child))
+    img, cx, cy, R, s, A = _c1_geometry_counts(rng, W, H, n_rings, max_attempts=max_attempts)
+    return Frame(img, cx, cy, R, s, A, dict(PARAMS_C3), seed)
+
+
 def config3(seed: int = 2, n_frames: int = 64, max_attempts: int = 300_000) -> list[Frame]:
     """Batch of uint16 frames of uneven sizes from BATCH_SIZES, 50..800 disjoint rings each
     with the 256x256 geometry (R ~ U(10, 30), s = 1.5), intensities x1000 counts
     (background 200, amplitude 1000, Gaussian noise sigma 50), 12-bit."""
-    ss = np.random.SeedSequence(seed)
-    top = np.random.Generator(np.random.PCG64(ss))
-    children = ss.spawn(n_frames)
-    frames = []
-    for i in range(n_frames):
-        W, H = BATCH_SIZES[int(top.integers(0, len(BATCH_SIZES)))]
-        n_rings = int(top.integers(50, 801))
-        rng = np.random.Generator(np.random.PCG64(children[i]))
-        img, cx, cy, R, s, A = _c1_geometry_counts(rng, W, H, n_rings, max_attempts=max_attempts)
-        frames.append(Frame(img, cx, cy, R, s, A, dict(PARAMS_C3), seed))
-    return frames
+    return [config3_frame(item, seed, max_attempts) for item in config3_plan(seed, n_frames)]
 
 
 def config2_batch(seed0: int = 1000, n_frames: int = 64, W: int = 1024, H: int = 1024) -> list[Frame]:
