@@ -147,7 +147,7 @@ rd_status rd_detect_batch(rd_handle h, const rd_frame* frames, int32_t n, const 
 typedef struct {
     int32_t stencil_tile;  /* ridge kernel tile: 0 = 64x32 (64x16 when ceil(4 sigma) > 8),
                               1 = 32x32, 2 = 64x16                                          */
-    int32_t vote_lds_kb;   /* LDS for one tile's vote histograms, 16..52 (KiB); more levels
+    int32_t vote_lds_kb;   /* LDS for one tile's vote histograms, 16..80 (KiB); more levels
                               per pass with more LDS                                         */
     int32_t use_graph;     /* 1: capture and replay launch sequences as HIP graphs (needs a
                               non-null stream)                                               */

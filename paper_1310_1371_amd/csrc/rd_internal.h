@@ -114,8 +114,8 @@ void stencil_tile_dims(int variant, int rg, bool dense, int* tw, int* th);
 hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, int variant, bool dense, hipStream_t s);
 
 constexpr int VOTE_TILE = 32;
-constexpr int VOTE_LDS_MAX = 52 * 1024;   // dynamic LDS of the vote kernel: with ~106 KB static, ~158 of 160 KB
-constexpr int VOTE_NLEV_MAX = 12;          // accumulator levels per level chunk
+constexpr int VOTE_LDS_MAX = 80 * 1024;   // dynamic LDS of the vote kernel: with ~79 KB static, ~159 of 160 KB
+constexpr int VOTE_NLEV_MAX = 20;          // accumulator levels per level chunk
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
 hipError_t vote_prepare();   // one-time kernel attributes (outside any graph capture)
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s);

@@ -81,7 +81,6 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     constexpr int BINS_PER_SIDE = ((T + 2 + 2 * K_MAX + 2 * (R_LIMIT + 2)) >> BIN_SHIFT) + 2;
     static_assert(BINS_PER_SIDE * BINS_PER_SIDE <= NT, "one thread per candidate bin");
     extern __shared__ __align__(16) uint32_t sA[];           // u16 histogram, two per word
-    __shared__ uint16_t sMap[NLEV_MAX * SR2];                // strong index + 1 per score voxel
     __shared__ uint32_t sRidXY[RCAP];
     __shared__ uint32_t sRidQ[RCAP];
     __shared__ uint32_t sRidR[RCAP];                         // level ranges of both signs (u8 pairs)
@@ -117,7 +116,6 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         sKt[i] = a.ktab[i];
     }
     for (int i = tid; i <= a.nchunks; i += NT) sChunk[i] = a.chunk_start[i];
-    for (int i = tid; i < (NLEV_MAX * SR2) / 2; i += NT) reinterpret_cast<uint32_t*>(sMap)[i] = 0u;
     __syncthreads();
 
     const int lbase = a.lbase;
@@ -309,14 +307,14 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             // over whole accumulator rows, flattened over (level, row, 16-byte column)
             const int SHh = sy1 - sy0;
             {
-                const int n8 = AWP >> 3;                          // 16-byte columns per row
+                const int c8lo = (sx0 - ax0) >> 3, n8 = ((sx1 - 1 - ax0) >> 3) - c8lo + 1;   // 16-byte columns
                 const int rows = nlev * SHh;
                 const uint32_t units = static_cast<uint32_t>(rows * n8);
                 const uint32_t m8 = 0xffffffffu / static_cast<uint32_t>(n8) + 1u;    // x / n8 by mulhi
                 const uint32_t mS = 0xffffffffu / static_cast<uint32_t>(SHh) + 1u;
                 const uint4* a4 = reinterpret_cast<const uint4*>(sA);
                 for (uint32_t u = tid; u < units; u += NT) {
-                    const uint32_t rl = __umulhi(u, m8), c8 = u - rl * n8;
+                    const uint32_t rl = __umulhi(u, m8), c8 = u - rl * n8 + c8lo;
                     const uint32_t li = __umulhi(rl, mS), r = rl - li * SHh;
                     const int vy = sy0 + static_cast<int>(r);
                     const uint4 w4 = a4[((li * plane + (vy - ay0) * AWP) >> 3) + c8];
@@ -423,7 +421,6 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         if (j < static_cast<uint32_t>(SCAP)) {
                             sStrongS[j] = sc;
                             sStrongId[j] = e;
-                            sMap[li * SR2 + sidx] = static_cast<uint16_t>(j + 1);
                         } else {
                             atomicOr(a.error, 1u);
                         }
@@ -447,23 +444,22 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 if (sxr < 1 || sxr > T || syr < 1 || syr > T) continue;
                 const int vx = x0 - 1 + sxr, vy = y0 - 1 + syr;
                 if (vx >= W || vy >= H) continue;
-                uint16_t nb[27];
-#pragma unroll
-                for (int k = 0; k < 27; ++k) {
-                    const int dl = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
-                    nb[k] = sMap[(li + dl) * SR2 + sidx + dy * SR + dx];
-                }
+                // the neighbours that matter are strong too (a weaker one cannot win), so
+                // the comparison runs over the chunk's strong list
                 const unsigned long long sv = sStrongS[j];
                 bool peak = true;
-#pragma unroll
-                for (int k = 0; k < 27; ++k) {
-                    if (k == 13 || !nb[k]) continue;
-                    const int dl = k / 9 - 1;
-                    const unsigned long long su = sStrongS[nb[k] - 1];
+                for (int k = 0; k < ns && peak; ++k) {
+                    if (k == j) continue;
+                    const uint32_t eu = sStrongId[k];
+                    const int dl = static_cast<int>(eu >> 16) - li;
+                    const int su_idx = static_cast<int>(eu & 0xffffu);
+                    const int dy = su_idx / SR - syr, dx = su_idx % SR - sxr;
+                    if (dl < -1 || dl > 1 || dy < -1 || dy > 1 || dx < -1 || dx > 1) continue;
                     const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
-                    const unsigned long long rhs = su * static_cast<unsigned long long>(lm);
-                    // neighbours before v in (r, y, x) order are the first 13 of the box
-                    if (k < 13 ? !(lhs > rhs) : !(lhs >= rhs)) peak = false;
+                    const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(lm);
+                    // neighbours before v in (r, y, x) order must be strictly below it
+                    const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+                    if (earlier ? !(lhs > rhs) : !(lhs >= rhs)) peak = false;
                 }
                 if (peak) {
                     const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
@@ -473,11 +469,6 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         a.peaks[fd.peak0 + idx] = pk;
                     }
                 }
-            }
-            __syncthreads();
-            for (int j = tid; j < ns; j += NT) {          // leave the map clean for the next chunk
-                const uint32_t e = sStrongId[j];
-                sMap[(e >> 16) * SR2 + (e & 0xffff)] = 0;
             }
             __syncthreads();
         }

@@ -130,7 +130,7 @@ class Detector:
         buf = np.frombuffer(out, dtype=RING_DTYPE)
         return [buf[i * cap:i * cap + counts[i]].copy() for i in range(n)]
 
-    def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = 52, use_graph: bool = True):
+    def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = 80, use_graph: bool = True):
         t = N.RdTuning(stencil_tile, vote_lds_kb, 1 if use_graph else 0)
         N.check(self._lib.rd_set_tuning(self._h, ctypes.byref(t)), "rd_set_tuning")
 
