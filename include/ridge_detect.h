@@ -143,12 +143,16 @@ rd_status rd_detect_batch(rd_handle h, const rd_frame* frames, int32_t n, const 
                           rd_ring* out, const int64_t* out_offsets, const int32_t* capacities,
                           int32_t* n_rings);
 
-/* Launch configuration choices.  None changes any result. */
+/* Largest vote_lds_kb: what the vote kernel's own LDS leaves of a compute unit's 160 KiB. */
+#define RD_VOTE_LDS_KB_MAX 66
+
+/* Launch configuration choices.  None changes any result.  A new context starts at
+ * {0, RD_VOTE_LDS_KB_MAX, 1}. */
 typedef struct {
     int32_t stencil_tile;  /* ridge kernel tile: 0 = 64x32 (64x16 when ceil(4 sigma) > 8),
                               1 = 32x32, 2 = 64x16                                          */
-    int32_t vote_lds_kb;   /* LDS for one tile's vote histograms, 16..80 (KiB); more levels
-                              per pass with more LDS                                         */
+    int32_t vote_lds_kb;   /* LDS for one tile's vote histograms, 16..RD_VOTE_LDS_KB_MAX
+                              (KiB); more levels per pass with more LDS                      */
     int32_t use_graph;     /* 1: capture and replay launch sequences as HIP graphs (needs a
                               non-null stream)                                               */
 } rd_tuning;

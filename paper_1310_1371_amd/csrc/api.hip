@@ -631,7 +631,8 @@ rd_status rd_autotune(rd_handle h, const rd_frame* frames, int32_t n, const rd_p
     const rd_tuning saved = h->tune;
     rd_tuning winner = saved;
     double best_s = 1e300;
-    static const int kLds[] = {44, 56, 68, 80};
+    static const int kLds[] = {RD_VOTE_LDS_KB_MAX - 36, RD_VOTE_LDS_KB_MAX - 24, RD_VOTE_LDS_KB_MAX - 12,
+                               RD_VOTE_LDS_KB_MAX};
     for (int v = 0; v < STENCIL_VARIANTS; ++v) {
         for (int kb : kLds) {
             if (kb * 1024 > VOTE_LDS_MAX) continue;

@@ -89,7 +89,7 @@ struct rd_ctx {
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
     // tuning and the cached level tables
-    rd_tuning tune{0, 80, 1};
+    rd_tuning tune{0, RD_VOTE_LDS_KB_MAX, 1};
     rd_params tab_params{};
     size_t tab_budget = 0;
     bool tab_valid = false;

@@ -53,6 +53,12 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave
     return base + inc - v;
 }
 
+// floor(x / d) by a multiply-high with m = floor((2^32 - 1) / d) + 1, exact while x * d < 2^32
+// (m wraps to 0 for d = 1, which takes x itself)
+__device__ __forceinline__ uint32_t div_mulhi(uint32_t x, uint32_t d, uint32_t m) {
+    return d == 1u ? x : __umulhi(x, m);
+}
+
 __device__ __forceinline__ uint32_t get_u16(const uint32_t* s, int idx) {
     return (s[idx >> 1] >> ((idx & 1) << 4)) & 0xffffu;
 }
@@ -62,7 +68,8 @@ constexpr int NLEV_MAX = VOTE_NLEV_MAX;    // accumulator levels per level chunk
 constexpr int RCAP = 3072;                 // ridge records staged per tile
 constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the per-level fallback)
 constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
-constexpr int WB = K_MAX + 1;              // centre of the padded weight row
+constexpr int WC = K_MAX + 8;              // centre tap of the padded weight row
+constexpr int NWW = WC + 4;                // u16 pairs per weight row: taps 0 .. 2 WC + 7
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
 
@@ -84,6 +91,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ uint32_t sRidXY[RCAP];
     __shared__ uint32_t sRidQ[RCAP];
     __shared__ uint32_t sRidR[RCAP];                         // level ranges of both signs (u8 pairs)
+    __shared__ uint16_t sOrd[2 * RCAP];                      // (ridge, sign) items by first level
+    __shared__ uint32_t sKey[256];                           // counting-sort offsets
+    __shared__ uint32_t sNact;                               // items with a non-empty level range
     // hotspot list and scores
     __shared__ __align__(16) uint8_t sScratch[HCAP * 12];
     uint32_t* const sHot = reinterpret_cast<uint32_t*>(sScratch);                        // (level << 16) | index
@@ -94,10 +104,10 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ uint32_t sBinPre[NT + 1];
     __shared__ uint32_t sBinId[NT];
     __shared__ uint16_t sWt[LMAX][K_MAX + 1];                // 15-bit weight factors
-    // per chunk level: weights W(|o - WB|) for o = 0 .. 2 WB + 1 (zero beyond K), as u16 pairs
-    // starting at even (sWpE) and odd (sWpO) o, for two-tap dot products
-    __shared__ uint32_t sWpE[NLEV_MAX][WB + 1];
-    __shared__ uint32_t sWpO[NLEV_MAX][WB + 1];
+    // per chunk level: weights W(|o - WC|) of taps o = 0 .. 2 WC + 8 (zero beyond K), as u16
+    // pairs starting at even (sWpE) and odd (sWpO) taps, for two-tap dot products
+    __shared__ uint32_t sWpE[NLEV_MAX][NWW];
+    __shared__ uint32_t sWpO[NLEV_MAX][NWW];
     __shared__ int sTile;
     __shared__ unsigned long long sThr[LMAX];
     __shared__ int32_t sKt[LMAX];
@@ -121,7 +131,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     const int lbase = a.lbase;
     const int r_lo = sChunk[0], r_hi = sChunk[a.nchunks];     // peak levels [r_lo, r_hi)
     const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
-    unsigned long long st_votes = 0, st_hot = 0, st_strong = 0, st_taps = 0;   // statistics
+    uint32_t st_votes = 0;                                              // statistics
+    unsigned long long st_hot = 0, st_strong = 0, st_taps = 0;
 
     for (;;) {
         // tiles are taken from a queue: their cost varies with the number of hotspots
@@ -189,14 +200,14 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
                 for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
             }
-            for (int i = tid; i < nlev * (WB + 1); i += NT) {
-                const int li = i / (WB + 1), j = i - li * (WB + 1);
+            for (int i = tid; i < nlev * NWW; i += NT) {
+                const int li = i / NWW, j = i - li * NWW;
                 const int lg = l0 + li - lbase, K = sKt[lg];
                 uint32_t wl[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const int o = 2 * j + k, d = o > WB ? o - WB : WB - o;
-                    wl[k] = (o <= 2 * WB + 1 && d <= K) ? static_cast<uint32_t>(sWt[lg][d]) : 0u;
+                    const int o = 2 * j + k, d = o > WC ? o - WC : WC - o;
+                    wl[k] = d <= K ? static_cast<uint32_t>(sWt[lg][d]) : 0u;
                 }
                 sWpE[li][j] = wl[0] | (wl[1] << 16);
                 sWpO[li][j] = wl[1] | (wl[2] << 16);
@@ -263,41 +274,77 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         }
                         sRidR[j] = rr;
                     }
+                    for (int i = tid; i < 256; i += NT) sKey[i] = 0u;
+                    __syncthreads();
+                    // order the (ridge, sign) items whose range meets the tile by first level
+                    // (counting sort): the lanes of a wave then run level loops of similar
+                    // extent; the items that miss the tile (key 255, most of them) are dropped
+                    for (int it = tid; it < 2 * pn; it += NT) {
+                        const uint32_t key = (sRidR[it >> 1] >> (16 * (it & 1))) & 0xffu;
+                        if (key != 255u) atomicAdd(&sKey[key], 1u);   // empty items are not placed
+                    }
+                    __syncthreads();
+                    if (tid < 64) {
+                        uint32_t k4[4];
+                        uint32_t sum = 0;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            k4[e] = sKey[4 * tid + e];
+                            sum += k4[e];
+                        }
+                        const uint32_t inc = wave_incl_scan(sum, lane);
+                        uint32_t run = inc - sum;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            sKey[4 * tid + e] = run;
+                            if (4 * tid + e == 255) sNact = run;
+                            run += k4[e];
+                        }
+                    }
+                    __syncthreads();
+                    for (int it = tid; it < 2 * pn; it += NT) {
+                        const uint32_t key = (sRidR[it >> 1] >> (16 * (it & 1))) & 0xffu;
+                        if (key != 255u) sOrd[atomicAdd(&sKey[key], 1u)] = static_cast<uint16_t>(it);
+                    }
                     __syncthreads();
                 }
                 // votes: each staged ridge and sign over its level range, clipped to this chunk;
                 // the region test below rejects the few votes that land in the tile's widest
                 // region but outside this chunk's
-                for (int j = tid; j < pn; j += NT) {
-                    const uint32_t rr = sRidR[j];
-                    const int la0 = static_cast<int>(rr & 0xffu) + lbase, lb0 = static_cast<int>((rr >> 8) & 0xffu) + lbase;
-                    const int la1 = static_cast<int>((rr >> 16) & 0xffu) + lbase, lb1 = static_cast<int>(rr >> 24) + lbase;
-                    const bool any0 = max(la0, l0) <= min(lb0, l1), any1 = max(la1, l0) <= min(lb1, l1);
-                    if (!any0 && !any1) continue;
-                    const uint32_t xy = sRidXY[j], q = sRidQ[j];
-                    const int x = xy & 0xffffu, y = xy >> 16;
+                const int nact = static_cast<int>(sNact);
+                for (int k = tid; k < nact; k += NT) {
+                    const int it = sOrd[k];
+                    const int jr = it >> 1, sg = it & 1;
+                    const uint32_t rr = sRidR[jr] >> (16 * sg);
+                    const int la_raw = static_cast<int>(rr & 0xffu) + lbase;
+                    if (la_raw > l1) break;                       // the rest start later still
+                    const int la = max(la_raw, l0), lb = min(static_cast<int>((rr >> 8) & 0xffu) + lbase, l1);
+                    if (la > lb) continue;
+                    const uint32_t xy = sRidXY[jr], q = sRidQ[jr];
+                    const int x = (xy & 0xffffu) - ax0, y = (xy >> 16) - ay0;
                     const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
-#pragma unroll
-                    for (int sg = 0; sg < 2; ++sg) {
-                        const int la = max(sg ? la1 : la0, l0), lb = min(sg ? lb1 : lb0, l1);
-                        const int s = sg ? -1 : 1;
-                        // fixed-point offsets, advanced by q per level; the mirrored vote is
-                        // x - rho(l, q), not x + rho(l, -q) (they differ at exact halves)
-                        int accx = la * qx + 8192, accy = la * qy + 8192;
-                        int base = (la - l0) * plane;
-                        for (int l = la; l <= lb; ++l) {
-                            const int u = x + s * (accx >> 14) - ax0;
-                            const int v = y + s * (accy >> 14) - ay0;
-                            if (static_cast<unsigned>(u) < static_cast<unsigned>(AW) &&
-                                static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
-                                const int idx = base + v * AWP + u;
-                                atomicAdd(&sA[idx >> 1], 1u << ((idx & 1) << 4));
-                                ++st_votes;
-                            }
-                            accx += qx;
-                            accy += qy;
-                            base += plane;
+                    // fixed-point offsets, advanced by q per level.  The mirrored vote is
+                    // x - floor((l q + 2^13) / 2^14) (not x + rho(l, -q): they differ at exact
+                    // halves), which equals x + floor((-l q + 2^13 - 1) / 2^14), so both signs
+                    // take the same form with a signed step and rounding constant
+                    const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
+                    const int rnd = sg ? 8191 : 8192;
+                    int accx = la * sqx + rnd, accy = la * sqy + rnd;
+                    // byte offsets of the u16 counters: 2 u within a row, row stride 2 AWP
+                    const int x2 = 2 * x, AW2 = 2 * AW, AWP2 = 2 * AWP;
+                    int base = 2 * (la - l0) * plane;
+                    for (int l = la; l <= lb; ++l) {
+                        const int u2 = x2 + 2 * (accx >> 14);
+                        const int v = y + (accy >> 14);
+                        if (static_cast<unsigned>(u2) < static_cast<unsigned>(AW2) &&
+                            static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
+                            const int b = base + static_cast<int>(__umul24(v, AWP2)) + u2;   // 0 <= v < AH
+                            atomicAdd(&sA[b >> 2], 1u << ((b & 2) << 3));
+                            ++st_votes;
                         }
+                        accx += sqx;
+                        accy += sqy;
+                        base += 2 * plane;
                     }
                 }
                 __syncthreads();
@@ -310,12 +357,12 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 const int c8lo = (sx0 - ax0) >> 3, n8 = ((sx1 - 1 - ax0) >> 3) - c8lo + 1;   // 16-byte columns
                 const int rows = nlev * SHh;
                 const uint32_t units = static_cast<uint32_t>(rows * n8);
-                const uint32_t m8 = 0xffffffffu / static_cast<uint32_t>(n8) + 1u;    // x / n8 by mulhi
+                const uint32_t m8 = 0xffffffffu / static_cast<uint32_t>(n8) + 1u;
                 const uint32_t mS = 0xffffffffu / static_cast<uint32_t>(SHh) + 1u;
                 const uint4* a4 = reinterpret_cast<const uint4*>(sA);
                 for (uint32_t u = tid; u < units; u += NT) {
-                    const uint32_t rl = __umulhi(u, m8), c8 = u - rl * n8 + c8lo;
-                    const uint32_t li = __umulhi(rl, mS), r = rl - li * SHh;
+                    const uint32_t rl = div_mulhi(u, n8, m8), c8 = u - rl * n8 + c8lo;
+                    const uint32_t li = div_mulhi(rl, SHh, mS), r = rl - li * SHh;
                     const int vy = sy0 + static_cast<int>(r);
                     const uint4 w4 = a4[((li * plane + (vy - ay0) * AWP) >> 3) + c8];
                     // largest of the eight counters by packed 16-bit maxima first
@@ -360,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             // ---- integer scores of the hotspots, then the strong (above-threshold) ones
             const uint32_t nh_all = sNh;
             const bool per_level = nh_all > static_cast<uint32_t>(HCAP);
-            const int rowsmax = 2 * Kc + 1;
+            const int nbm = ((2 * Kc + 7) >> 3) + 1;          // 8-column bands a window can span
             const int npass = per_level ? nlev : 1;
             for (int pass = 0; pass < npass; ++pass) {
                 if (per_level) {
@@ -381,30 +428,57 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     __syncthreads();
                 }
                 const int nh = static_cast<int>(min(sNh, static_cast<uint32_t>(HCAP)));
-                for (int task = tid; task < nh * rowsmax; task += NT) {
-                    const int h = task / rowsmax;
-                    const int dy = task - h * rowsmax - Kc;
+                // one task per hotspot, 8-column band of its window (16-byte aligned in the row)
+                // and half of the window's rows: the band's eight horizontal weights stay in
+                // registers while the task walks its rows with one 16-byte load each
+                const int ntk = 2 * nbm;
+                const uint32_t mB = 0xffffffffu / static_cast<uint32_t>(ntk) + 1u;
+                for (int task = tid; task < nh * ntk; task += NT) {
+                    const int h = static_cast<int>(div_mulhi(static_cast<uint32_t>(task), ntk, mB));
+                    const int sub = task - h * ntk, bi = sub >> 1, half = sub & 1;
                     const uint32_t e = sHot[h];
                     const int li = e >> 16, sidx = e & 0xffff;
                     const int lg = l0 + li - lbase;
                     const int K = sKt[lg];
-                    if (dy < -K || dy > K) continue;
                     const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
-                    const int yy = vy + dy;
-                    if (yy < ay0 || yy >= ay1) continue;
-                    // row sum over [vx - K, vx + K] clipped to the frame, two taps per step from
-                    // an even column; taps outside the window meet zero weights, the column past
-                    // the region's right edge is zero padding
-                    const int xs = max(vx - K, ax0), xe = min(vx + K, ax1 - 1);
-                    const int xw = xs - ((xs - ax0) & 1);
-                    const uint32_t* arow = sA + ((li * plane + (yy - ay0) * AWP) >> 1) + ((xw - ax0) >> 1);
-                    const int o = xw - vx + WB;                   // >= WB - K - 1 >= 0
+                    const int cs = max(vx - K, ax0) - ax0, ce = min(vx + K, ax1 - 1) - ax0;
+                    const int c0 = ((cs >> 3) + bi) << 3;          // band start, relative to ax0
+                    if (c0 > ce) continue;
+                    // taps of the band: columns c0 .. c0 + 7 meet weights W(|ax0 + c - vx|), zero
+                    // outside the window; columns past the region's right edge are zero padding
+                    const int o = ax0 + c0 - vx + WC;               // WC - K - 7 >= 1, o + 7 < 2 WC
                     const uint32_t* wp = (o & 1) ? &sWpO[li][o >> 1] : &sWpE[li][o >> 1];
-                    const int nw = ((xe - xw) >> 1) + 1;
-                    uint32_t rs = 0;
-                    for (int k = 0; k < nw; ++k) rs = dot2_u16(arow[k], wp[k], rs);
-                    st_taps += 2 * nw;
-                    if (rs) atomicAdd(&sHS[h], static_cast<unsigned long long>(sWt[lg][dy < 0 ? -dy : dy]) * rs);
+                    const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
+                    // rows vy - K .. vy (half 0) or vy + 1 .. vy + K (half 1), clipped to the region
+                    const int ylo = half ? vy + 1 : max(vy - K, ay0), yhi = half ? min(vy + K, ay1 - 1) : vy;
+                    const int rstep = AWP >> 3;
+                    const uint4* row = reinterpret_cast<const uint4*>(sA) + ((li * plane + (ylo - ay0) * AWP + c0) >> 3);
+                    const uint16_t* wv = &sWt[lg][0];
+                    unsigned long long acc = 0;
+                    auto band = [&](const uint4 q) {
+                        uint32_t rs = dot2_u16(q.x, w0, 0u);
+                        rs = dot2_u16(q.y, w1, rs);
+                        rs = dot2_u16(q.z, w2, rs);
+                        return dot2_u16(q.w, w3, rs);
+                    };
+                    int yy = ylo;
+                    for (; yy + 3 <= yhi; yy += 4) {           // four independent row loads in flight
+                        const uint4 q0 = row[0], q1 = row[rstep], q2 = row[2 * rstep], q3 = row[3 * rstep];
+                        row += 4 * rstep;
+                        const int d0 = yy - vy;
+                        acc += static_cast<unsigned long long>(wv[d0 < 0 ? -d0 : d0]) * band(q0);
+                        acc += static_cast<unsigned long long>(wv[d0 + 1 < 0 ? -d0 - 1 : d0 + 1]) * band(q1);
+                        acc += static_cast<unsigned long long>(wv[d0 + 2 < 0 ? -d0 - 2 : d0 + 2]) * band(q2);
+                        acc += static_cast<unsigned long long>(wv[d0 + 3 < 0 ? -d0 - 3 : d0 + 3]) * band(q3);
+                    }
+                    for (; yy <= yhi; ++yy) {
+                        const uint4 q = *row;
+                        row += rstep;
+                        const int dy = yy - vy;
+                        acc += static_cast<unsigned long long>(wv[dy < 0 ? -dy : dy]) * band(q);
+                    }
+                    st_taps += 8 * max(yhi - ylo + 1, 0);
+                    if (acc) atomicAdd(&sHS[h], acc);
                 }
                 __syncthreads();
                 for (int h = tid; h < nh; h += NT) {
@@ -561,6 +635,7 @@ hipError_t vote_prepare() {
 
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s) {
     if (a.total_vtiles <= 0 || a.nchunks <= 0) return hipSuccess;
+    if (lds > static_cast<size_t>(VOTE_LDS_MAX)) return hipErrorInvalidValue;   // beyond the opted-in size
     if (blocks > a.total_vtiles) blocks = a.total_vtiles;   // persistent blocks take tiles from the queue
     if (dump)
         hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(blocks), dim3(NT), lds, s, a);

@@ -66,6 +66,7 @@ class Detector:
         h = ctypes.c_void_p()
         N.check(self._lib.rd_create(ctypes.byref(info), ctypes.byref(h)), "rd_create")
         self._h = h
+        self.default_tuning = self.get_tuning()
         self.max_peaks = max_peaks
         self._rings = (N.RdRing * max_peaks)()
 
@@ -130,7 +131,10 @@ class Detector:
         buf = np.frombuffer(out, dtype=RING_DTYPE)
         return [buf[i * cap:i * cap + counts[i]].copy() for i in range(n)]
 
-    def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = 80, use_graph: bool = True):
+    def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = None, use_graph: bool = True):
+        """Launch choices (no result depends on them); vote_lds_kb None keeps the largest."""
+        if vote_lds_kb is None:
+            vote_lds_kb = self.default_tuning["vote_lds_kb"]
         t = N.RdTuning(stencil_tile, vote_lds_kb, 1 if use_graph else 0)
         N.check(self._lib.rd_set_tuning(self._h, ctypes.byref(t)), "rd_set_tuning")
 

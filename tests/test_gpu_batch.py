@@ -88,22 +88,34 @@ def test_batch_host_frames(bdet):
 
 
 @pytest.mark.parametrize("stencil_tile", [0, 1, 2])
-@pytest.mark.parametrize("vote_lds_kb", [24, 52, 80])
+@pytest.mark.parametrize("vote_lds_kb", [24, 44, None])
 def test_tuning_invariance(bdet, stencil_tile, vote_lds_kb):
     say(f"[tuning] stencil {stencil_tile} lds {vote_lds_kb}")
     f = synth.config2(seed=77, W=640, H=480, n_rings=80)
     img = torch.from_numpy(f.image).cuda()
-    bdet.set_tuning(stencil_tile=0, vote_lds_kb=80, use_graph=True)
+    bdet.set_tuning(stencil_tile=0, use_graph=True)
     ref = bdet.detect(img, f.params)
     xy0, q0, _ = bdet.ridges(img, f.params)
     bdet.set_tuning(stencil_tile=stencil_tile, vote_lds_kb=vote_lds_kb, use_graph=True)
     got = bdet.detect(img, f.params)
     xy1, q1, _ = bdet.ridges(img, f.params)
-    bdet.set_tuning(stencil_tile=0, vote_lds_kb=80, use_graph=True)
+    bdet.set_tuning(stencil_tile=0, use_graph=True)
     assert _same(ref, got)
     s0 = set(map(tuple, torch.cat([xy0, q0.int()], 1).cpu().numpy().tolist()))
     s1 = set(map(tuple, torch.cat([xy1, q1.int()], 1).cpu().numpy().tolist()))
     assert s0 == s1
+
+
+def test_tuning_beyond_the_lds_limit_is_rejected(bdet):
+    """The default is the largest histogram budget; one KiB more is refused on the host."""
+    top = bdet.default_tuning["vote_lds_kb"]
+    assert bdet.get_tuning()["vote_lds_kb"] == top
+    from paper_1310_1371_amd.native import RdError
+    with pytest.raises(RdError):
+        bdet.set_tuning(vote_lds_kb=top + 1)
+    with pytest.raises(RdError):
+        bdet.set_tuning(vote_lds_kb=15)
+    assert bdet.get_tuning()["vote_lds_kb"] == top
 
 
 @pytest.mark.parametrize("vote_lds_kb", [16, 32])
@@ -114,11 +126,11 @@ def test_accumulator_invariant_to_level_chunks(bdet, vote_lds_kb):
     xs, ys, qx, qy, _ = O.ridges(f.image, p)
     xy = np.stack([xs, ys], 1).astype(np.int32)
     q = np.stack([qx, qy], 1).astype(np.int16)
-    bdet.set_tuning(vote_lds_kb=80)
+    bdet.set_tuning()
     a0, s0 = bdet.accumulate(xy, q, 256, 256, p)
     bdet.set_tuning(vote_lds_kb=vote_lds_kb)
     a1, s1 = bdet.accumulate(xy, q, 256, 256, p)
-    bdet.set_tuning(vote_lds_kb=80)
+    bdet.set_tuning()
     assert torch.equal(a0, a1) and torch.equal(s0, s1)
 
 
@@ -126,8 +138,8 @@ def test_autotune_returns_a_valid_choice(bdet):
     say("[tuning] autotune")
     fs = _frames_u16()[:2]
     t = bdet.autotune([torch.from_numpy(f.image).cuda() for f in fs], fs[0].params, reps=1)
-    assert t["stencil_tile"] in (0, 1, 2) and 16 <= t["vote_lds_kb"] <= 80
-    bdet.set_tuning(stencil_tile=0, vote_lds_kb=80, use_graph=True)
+    assert t["stencil_tile"] in (0, 1, 2) and 16 <= t["vote_lds_kb"] <= bdet.default_tuning["vote_lds_kb"]
+    bdet.set_tuning(stencil_tile=0, use_graph=True)
 
 
 def test_batch_limits(bdet):
