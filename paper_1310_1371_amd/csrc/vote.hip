@@ -101,6 +101,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
 
     __shared__ unsigned long long sStrongS[SCAP];
     __shared__ uint32_t sStrongId[SCAP];
+    __shared__ uint8_t sBad[SCAP];                           // strong voxel beaten by a neighbour
     __shared__ uint32_t sBinPre[NT + 1];
     __shared__ uint32_t sBinId[NT];
     __shared__ uint16_t sWt[LMAX][K_MAX + 1];                // 15-bit weight factors
@@ -495,6 +496,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         if (j < static_cast<uint32_t>(SCAP)) {
                             sStrongS[j] = sc;
                             sStrongId[j] = e;
+                            sBad[j] = 0;
                         } else {
                             atomicOr(a.error, 1u);
                         }
@@ -509,20 +511,38 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 st_hot += nh_all;
                 st_strong += static_cast<unsigned long long>(ns);
             }
-            for (int j = tid; j < ns; j += NT) {
+            // a voxel is tested if its level is a peak level of this chunk and it lies in the tile
+            auto candidate = [&](int j, int& li, int& lm, int& sxr, int& syr) {
                 const uint32_t e = sStrongId[j];
-                const int li = e >> 16, sidx = e & 0xffff;
-                const int lm = l0 + li;
-                if (lm < rc0 || lm >= rc1) continue;
-                const int sxr = sidx % SR, syr = sidx / SR;
-                if (sxr < 1 || sxr > T || syr < 1 || syr > T) continue;
-                const int vx = x0 - 1 + sxr, vy = y0 - 1 + syr;
-                if (vx >= W || vy >= H) continue;
+                li = e >> 16;
+                lm = l0 + li;
+                const int sidx = e & 0xffff;
+                sxr = sidx % SR;
+                syr = sidx / SR;
+                return lm >= rc0 && lm < rc1 && sxr >= 1 && sxr <= T && syr >= 1 && syr <= T &&
+                       x0 - 1 + sxr < W && y0 - 1 + syr < H;
+            };
+            auto emit = [&](int j, int lm, int sxr, int syr) {
+                const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
+                if (idx < static_cast<uint32_t>(a.max_peaks)) {
+                    Peak pk;
+                    pk.a = x0 - 1 + sxr; pk.b = y0 - 1 + syr; pk.r = lm; pk.frame = f; pk.s = sStrongS[j];
+                    a.peaks[fd.peak0 + idx] = pk;
+                }
+            };
+            // G lanes per strong voxel, each comparing a slice of the list (a long list is the
+            // mark of a ring-centre tile, the slowest work of a launch)
+            const int gs = ns > 256 ? 1 : ns > 128 ? 2 : ns > 32 ? 3 : 0;
+            const int G = 1 << gs;
+            for (int task = tid; task < (ns << gs); task += NT) {
+                const int j = task >> gs, g = task & (G - 1);
+                int li, lm, sxr, syr;
+                if (!candidate(j, li, lm, sxr, syr)) continue;
                 // the neighbours that matter are strong too (a weaker one cannot win), so
                 // the comparison runs over the chunk's strong list
                 const unsigned long long sv = sStrongS[j];
                 bool peak = true;
-                for (int k = 0; k < ns && peak; ++k) {
+                for (int k = g; k < ns && peak; k += G) {
                     if (k == j) continue;
                     const uint32_t eu = sStrongId[k];
                     const int dl = static_cast<int>(eu >> 16) - li;
@@ -535,13 +555,17 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
                     if (earlier ? !(lhs > rhs) : !(lhs >= rhs)) peak = false;
                 }
-                if (peak) {
-                    const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
-                    if (idx < static_cast<uint32_t>(a.max_peaks)) {
-                        Peak pk;
-                        pk.a = vx; pk.b = vy; pk.r = lm; pk.frame = f; pk.s = sv;
-                        a.peaks[fd.peak0 + idx] = pk;
-                    }
+                if (G == 1) {
+                    if (peak) emit(j, lm, sxr, syr);
+                } else if (!peak) {
+                    sBad[j] = 1;
+                }
+            }
+            if (G > 1) {
+                __syncthreads();
+                for (int j = tid; j < ns; j += NT) {
+                    int li, lm, sxr, syr;
+                    if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
                 }
             }
             __syncthreads();
