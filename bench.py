@@ -38,9 +38,9 @@ from concurrent.futures import ProcessPoolExecutor
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# LDS atomic ceiling of the vote stage: 256 CUs x 32 LDS banks, one 32-bit atomic per bank per
-# clock, at 2.4 GHz
-LDS_ATOMIC_PEAK = 256 * 32 * 2.4e9
+# The fused vote / smoothing / peak kernel runs out of LDS (the accumulator never reaches HBM):
+# its ceiling is the LDS datapath, 256 CUs x 32 banks x 4 bytes per clock at 2.4 GHz
+LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "vote_c2_1024_traffic.md")
 
 
@@ -184,15 +184,24 @@ def main():
     torch.cuda.synchronize()
     dt_graph = time.perf_counter() - t0
 
-    # ---- roofline of the dominant kernel (the vote / smoothing / peak kernel)
+    # ---- roofline of the dominant kernel (the vote / smoothing / peak kernel).  Algorithmic
+    # LDS bytes per launch: every cell of the W x H x L accumulator is cleared and tested against
+    # T_int once (2 + 2 bytes of u16 counter), and every one of the 2 L N_ridge votes is one
+    # 4-byte atomic read-modify-write.  The smoothing taps at hotspots come on top and are not
+    # counted (a lower bound on the work).
     dom = max(kernel_ms, key=kernel_ms.get)
     L = p["r_max"] - p["r_min"] + 3
     votes = 2 * L * n_ridges
+    cells = W * H * L
+    lds_bytes = 4 * cells + 4 * votes
+    launch_s = kernel_ms["vote"] * 1e-3
     roof = {"bound": "alu", "kernel": "k_vote (votes, hotspot smoothing, 3x3x3 peaks)" if dom == "vote" else dom,
-            "achieved": votes / (kernel_ms["vote"] * 1e-3) / 1e12,
-            "peak": LDS_ATOMIC_PEAK / 1e12, "unit": "TOP/s",
-            "work": f"2 x {L} levels x {n_ridges} ridges = {votes} vote increments per launch; "
-                    f"peak = 256 CUs x 32 LDS atomics/clock x 2.4 GHz",
+            "achieved": lds_bytes / launch_s / 1e9,
+            "peak": LDS_PEAK_GBS, "unit": "GB/s",
+            "work": f"LDS bytes: 4 x {cells} accumulator cells ({W}x{H}x{L}, cleared + tested) + 4 x {votes} "
+                    f"votes (2 x {L} levels x {n_ridges} ridges) = {lds_bytes} per launch; peak = LDS datapath, "
+                    f"256 CUs x 128 B/clock x 2.4 GHz",
+            "votes_per_s": votes / launch_s,
             "launch_ms": kernel_ms["vote"],
             "traffic": traffic_from_profile(os.path.join(ROOT, "paper_1310_1371_amd", "csrc", "vote.hip"))}
     roof["frac"] = roof["achieved"] / roof["peak"]
