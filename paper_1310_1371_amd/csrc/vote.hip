@@ -1,25 +1,27 @@
 // Directed voting, radius-dependent smoothing, 1/r normalisation and 3x3x3 peak search
 // (method steps 3-4), fused in one LDS-resident kernel.
 //
-// A workgroup owns a T x T spatial tile and a chunk of consecutive radius levels
-// [rc0, rc1) in which it searches for peaks.  It needs the raw accumulator of levels
-// rc0 - 1 .. rc1 on the tile grown by 1 px (the 3x3x3 box) plus the smoothing half-width
-// K, so it:
-//   1. zeroes a u16 histogram for those levels in LDS (two counters per 32-bit word);
-//   2. gathers, from the 16x16 ridge bins whose pixels can reach the region at those
-//      radii, every ridge pixel and adds its +/- votes with LDS atomics (exact integers,
-//      the direction is the fixed-point code, offset floor((r q + 2^13) / 2^14));
-//   3. per level: compacts the hotspots (A > T_int) of the tile + 1 px, evaluates the
-//      integer score S_int = sum W(|dx|) W(|dy|) A with 15-bit weight factors (one window
-//      row per thread, merged with LDS 64-bit atomics), keeps scores above the level's
-//      integer threshold in a 3-level rotating map, and runs the 3x3x3 comparison for the
-//      previous level (scores at different levels compare as S_int / r, exactly, by
-//      cross-multiplication; a plateau keeps its first voxel in (r, y, x) order).
-// The dense accumulator volume never exists in memory: this is the GPU form of the
-// paper's rotating three-level sub-spaces with hotspot-only processing.
+// One persistent workgroup per CU takes T x T spatial tiles from a queue.  For each tile it
+// stages, once, the ridge records of the 16x16 bins whose pixels can vote into the tile's
+// widest accumulator region, with each sign's level range clipped to that region, and orders
+// the (ridge, sign) items that can reach the tile by first level.  It then walks the level
+// chunks; a chunk of peak levels [rc0, rc1) needs the raw accumulator of levels rc0 - 1 .. rc1
+// on the tile grown by 1 px (the 3x3x3 box) plus the smoothing half-width K, so per chunk it:
+//   1. clears a u16 histogram of those levels in LDS (two counters per 32-bit word);
+//   2. adds every item's votes over its level range with LDS atomics (exact integers: the
+//      direction is the fixed-point code, offset floor((r q + 2^13) / 2^14));
+//   3. lists the hotspots (A > T_int) of the tile + 1 px with 16-byte scans;
+//   4. evaluates the integer score S_int = sum W(|dx|) W(|dy|) A of each hotspot with 15-bit
+//      weight factors, in tasks of one 8-column band of the window and half its rows, and
+//      keeps the scores above the level's integer threshold in a "strong" list;
+//   5. tests each strong voxel of the peak levels against the strong voxels of its 3x3x3 box
+//      (scores at different levels compare as S_int / r, exactly, by cross-multiplication; a
+//      plateau keeps its first voxel in (r, y, x) order).
+// The dense accumulator volume never exists in memory: this is the GPU form of the paper's
+// rotating three-level sub-spaces with hotspot-only processing.
 //
 // A neighbour whose score is at or below the threshold can never beat a candidate, which
-// is above it, so keeping only above-threshold scores leaves every decision unchanged.
+// is above it, so comparing against the strong voxels only leaves every decision unchanged.
 #include "rd_internal.h"
 
 namespace rd {
