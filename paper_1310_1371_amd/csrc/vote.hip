@@ -184,25 +184,19 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         sBinId[tid] = bin_local;
         if (tid == 0) sBinPre[NT] = total;
         const int npieces = static_cast<int>((total + RCAP - 1) / RCAP);
-        __syncthreads();
 
-        for (int c = 0; c < a.nchunks; ++c) {
-            const int rc0 = sChunk[c], rc1 = sChunk[c + 1];
-            const int l0 = rc0 - 1, l1 = rc1;                // accumulator levels, inclusive
+        // clear chunk c's histogram, fill its weight rows and empty its hotspot list; chunk 0
+        // here, chunk c + 1 during chunk c's 3x3x3 phase, which touches none of these
+        auto prepare = [&](int c) {
+            const int l0 = sChunk[c] - 1, l1 = sChunk[c + 1];
             const int nlev = l1 - l0 + 1;
-            const int Kc = sKt[l1 - lbase];                   // widest window of the chunk
-            const int ax0 = max(sx0 - Kc, 0), ax1 = min(sx1 + Kc, W);
-            const int ay0 = max(sy0 - Kc, 0), ay1 = min(sy1 + Kc, H);
-            const int AW = ax1 - ax0, AH = ay1 - ay0;
-            const int AWP = (AW + 8) & ~7;                    // 16-byte rows, >= 1 zero column
-            const int plane = AWP * AH;                       // u16 per level, multiple of 8
-            {
-                const int words = (nlev * plane) >> 1;
-                uint4* a4 = reinterpret_cast<uint4*>(sA);
-                const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-                for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
-                for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
-            }
+            const int Kc = sKt[l1 - lbase];
+            const int AW = min(sx1 + Kc, W) - max(sx0 - Kc, 0), AH = min(sy1 + Kc, H) - max(sy0 - Kc, 0);
+            const int words = (nlev * ((AW + 8) & ~7) * AH) >> 1;
+            uint4* a4 = reinterpret_cast<uint4*>(sA);
+            const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+            for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
+            for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
             for (int i = tid; i < nlev * NWW; i += NT) {
                 const int li = i / NWW, j = i - li * NWW;
                 const int lg = l0 + li - lbase, K = sKt[lg];
@@ -215,12 +209,21 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 sWpE[li][j] = wl[0] | (wl[1] << 16);
                 sWpO[li][j] = wl[1] | (wl[2] << 16);
             }
-            if (tid == 0) {
-                sNh = 0;
-                sNs = 0;
-            }
-            __syncthreads();
+            if (tid == 0) sNh = 0;
+        };
+        prepare(0);
+        __syncthreads();
 
+        for (int c = 0; c < a.nchunks; ++c) {
+            const int rc0 = sChunk[c], rc1 = sChunk[c + 1];
+            const int l0 = rc0 - 1, l1 = rc1;                // accumulator levels, inclusive
+            const int nlev = l1 - l0 + 1;
+            const int Kc = sKt[l1 - lbase];                   // widest window of the chunk
+            const int ax0 = max(sx0 - Kc, 0), ax1 = min(sx1 + Kc, W);
+            const int ay0 = max(sy0 - Kc, 0), ay1 = min(sy1 + Kc, H);
+            const int AW = ax1 - ax0, AH = ay1 - ay0;
+            const int AWP = (AW + 8) & ~7;                    // 16-byte rows, >= 1 zero column
+            const int plane = AWP * AH;                       // u16 per level, multiple of 8
             // ---- votes of the staged ridges (staged once per tile unless they need pieces)
             for (int pc = 0; pc < npieces; ++pc) {
                 const uint32_t pbase = static_cast<uint32_t>(pc) * RCAP;
@@ -356,6 +359,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             // ---- hotspots (A > T_int) of the score region: 16-byte loads (eight counters)
             // over whole accumulator rows, flattened over (level, row, 16-byte column)
             const int SHh = sy1 - sy0;
+            if (tid == 0) sNs = 0;                            // last read by the previous 3x3x3 phase
             {
                 const int c8lo = (sx0 - ax0) >> 3, n8 = ((sx1 - 1 - ax0) >> 3) - c8lo + 1;   // 16-byte columns
                 const int rows = nlev * SHh;
@@ -570,6 +574,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
                 }
             }
+            if (c + 1 < a.nchunks) prepare(c + 1);
             __syncthreads();
         }
     }
@@ -580,11 +585,21 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             v += __shfl_xor(v, o, 64);
             tp += __shfl_xor(tp, o, 64);
         }
+        // per wave, then per block: one device atomic per counter and block (thousands of
+        // same-address atomics at the end of the launch would serialise behind the last tile)
+        __shared__ unsigned long long sRed[NW][2];
         if (lane == 0) {
+            sRed[tid >> 6][0] = v;
+            sRed[tid >> 6][1] = tp;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < NW; ++w) {
+                v += sRed[w][0];
+                tp += sRed[w][1];
+            }
             atomicAdd(&a.stats[0], v);
             atomicAdd(&a.stats[3], tp);
-        }
-        if (tid == 0) {
             atomicAdd(&a.stats[1], st_hot);
             atomicAdd(&a.stats[2], st_strong);
         }
