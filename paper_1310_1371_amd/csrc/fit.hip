@@ -1,9 +1,9 @@
 // Ridge classification and sub-pixel circle fit (method step 5).
 //
-// One wavefront per peak (a, b, r): it visits the 16x16 ridge bins that overlap the
+// One workgroup per peak (a, b, r): it visits the 16x16 ridge bins that overlap the
 // annulus' bounding box, takes the ridge pixels with (max(r-w,0))^2 <= (x-a)^2 + (y-b)^2
 // <= (r+w)^2 (an exact integer test; a ridge pixel may belong to several peaks), sums the
-// nine normal-equation moments of the algebraic (Kasa) fit exactly in int64, and lane 0
+// nine normal-equation moments of the algebraic (Kasa) fit exactly in int64, and one thread
 // solves the 3x3 system in fp64.
 #include "rd_internal.h"
 
@@ -45,9 +45,40 @@ __device__ bool solve3(double M[3][3], double rhs[3], double x[3]) {
     return true;
 }
 
-__global__ __launch_bounds__(64) void k_fit(FitArgs a) {
-    const int lane = threadIdx.x;
-    if (blockIdx.x == 0 && lane == 0 && a.counts_out) {
+constexpr int FNT = 256;   // threads per peak
+
+// Exclusive prefix over the block; *total receives the sum.  Contains __syncthreads.
+__device__ __forceinline__ uint32_t fit_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t n = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += n;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < FNT / 64; ++w) {
+        if (w < wave) base += s_wave[w];
+        tot += s_wave[w];
+    }
+    *total = tot;
+    return base + inc - v;
+}
+
+// One workgroup per peak.  The ridge slots of the bins in the annulus' bounding box are
+// flattened (a prefix over the bin counts, up to FNT bins per round) so that every thread
+// issues independent loads; the nine moments are summed per thread, then per wave, then
+// over the workgroup.
+__global__ __launch_bounds__(FNT) void k_fit(FitArgs a) {
+    __shared__ uint32_t sPre[FNT + 1];
+    __shared__ int64_t sBinBase[FNT];
+    __shared__ uint32_t sWave[FNT / 64];
+    __shared__ int64_t sMom[FNT / 64][9];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (blockIdx.x == 0 && tid == 0 && a.counts_out) {
         for (int f = 0; f < a.nframes; ++f) a.counts_out[f] = a.peak_count[f];
         a.counts_out[a.nframes] = a.error ? *a.error : 0u;
     }
@@ -58,31 +89,58 @@ __global__ __launch_bounds__(64) void k_fit(FitArgs a) {
             const Peak pk = a.peaks[fd.peak0 + p];
             const int pa = pk.a, pb = pk.b, r = pk.r;
             const int ro = r + a.w, ri = max(r - a.w, 0);
-            const int ro2 = ro * ro, ri2 = ri * ri;
+            const int64_t ro2 = static_cast<int64_t>(ro) * ro, ri2 = static_cast<int64_t>(ri) * ri;
             const int bxlo = max((pa - ro) >> BIN_SHIFT, 0), bxhi = min((pa + ro) >> BIN_SHIFT, fd.nbx - 1);
             const int bylo = max((pb - ro) >> BIN_SHIFT, 0), byhi = min((pb + ro) >> BIN_SHIFT, fd.nby - 1);
-            int64_t n = 0, su = 0, sv = 0, suu = 0, suv = 0, svv = 0, sz = 0, suz = 0, svz = 0;
+            int64_t m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // n, su, sv, suu, suv, svv, sz, suz, svz
             const int nbxr = bxhi - bxlo + 1;
             const int nbin = nbxr * (byhi - bylo + 1);
-            for (int bi = lane; bi < nbin; bi += 64) {     // one bin per lane
-                const int by = bylo + bi / nbxr, bx = bxlo + bi % nbxr;
-                const int64_t bin = fd.bin0 + (int64_t)by * fd.nbx + bx;
-                const uint32_t cnt = min(a.bin_count[bin], static_cast<uint32_t>(BIN_CAP));
-                for (uint32_t i = 0; i < cnt; ++i) {
-                    const uint32_t xy = a.rxy[bin * BIN_CAP + i];
+            for (int b0 = 0; b0 < nbin; b0 += FNT) {       // rounds of up to FNT bins
+                const int bi = b0 + tid;
+                uint32_t cnt = 0;
+                int64_t bin = 0;
+                if (bi < nbin) {
+                    const int by = bylo + bi / nbxr, bx = bxlo + bi % nbxr;
+                    bin = fd.bin0 + static_cast<int64_t>(by) * fd.nbx + bx;
+                    cnt = min(a.bin_count[bin], static_cast<uint32_t>(BIN_CAP));
+                }
+                uint32_t total;
+                const uint32_t pre = fit_excl_scan(cnt, sWave, &total);
+                sPre[tid] = pre;
+                sBinBase[tid] = bin * BIN_CAP;
+                if (tid == 0) sPre[FNT] = total;
+                __syncthreads();
+                for (uint32_t k = tid; k < total; k += FNT) {
+                    int lo = 0, hi = FNT;                   // largest lo with sPre[lo] <= k
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sPre[mid] <= k) lo = mid; else hi = mid;
+                    }
+                    const uint32_t xy = a.rxy[sBinBase[lo] + (k - sPre[lo])];
                     const int64_t u = static_cast<int>(xy & 0xffffu) - pa;
                     const int64_t v = static_cast<int>(xy >> 16) - pb;
                     const int64_t z = u * u + v * v;
                     if (z >= ri2 && z <= ro2) {
-                        n += 1; su += u; sv += v; suu += u * u; suv += u * v; svv += v * v;
-                        sz += z; suz += u * z; svz += v * z;
+                        m[0] += 1; m[1] += u; m[2] += v; m[3] += u * u; m[4] += u * v; m[5] += v * v;
+                        m[6] += z; m[7] += u * z; m[8] += v * z;
                     }
                 }
+                __syncthreads();                              // sPre is rewritten next round
             }
-            n = wave_sum64(n); su = wave_sum64(su); sv = wave_sum64(sv);
-            suu = wave_sum64(suu); suv = wave_sum64(suv); svv = wave_sum64(svv);
-            sz = wave_sum64(sz); suz = wave_sum64(suz); svz = wave_sum64(svz);
-            if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) m[i] = wave_sum64(m[i]);
+            if (lane == 0)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) sMom[wave][i] = m[i];
+            __syncthreads();
+            if (tid == 0) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    m[i] = sMom[0][i];
+                    for (int w = 1; w < FNT / 64; ++w) m[i] += sMom[w][i];
+                }
+                const int64_t n = m[0], su = m[1], sv = m[2], suu = m[3], suv = m[4], svv = m[5];
+                const int64_t sz = m[6], suz = m[7], svz = m[8];
                 double cx = pa, cy = pb, rr = r;
                 int ok = 0;
                 if (n >= a.min_pts) {
@@ -112,6 +170,7 @@ __global__ __launch_bounds__(64) void k_fit(FitArgs a) {
                 ring.fit_ok = ok;
                 a.rings[fd.peak0 + p] = ring;
             }
+            __syncthreads();                                  // sMom is rewritten by the next peak
         }
     }
 }
@@ -119,7 +178,7 @@ __global__ __launch_bounds__(64) void k_fit(FitArgs a) {
 }  // namespace
 
 hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_fit, dim3(blocks), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_fit, dim3(blocks), dim3(FNT), 0, s, a);
     return hipGetLastError();
 }
 
