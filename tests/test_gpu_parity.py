@@ -45,11 +45,19 @@ def _tail():
     return synth.Frame(img.astype(np.float32), cx, cy, R, s, A, dict(synth.PARAMS_C1), 0)
 
 
+def _big_ring():
+    """300 x 300 float32 with one ring of radius 123 px and radius bins 100-126 (the largest
+    r_max): the fit visits 17 x 17 ridge bins, more than one round of the fit's bin list."""
+    f = synth.single_ring(300, 300, 150.3, 149.6, 123.0)
+    return synth.Frame(f.image, f.cx, f.cy, f.R, f.s, f.A, dict(f.params, r_min=100, r_max=126), 0)
+
+
 CASES = {
     "c1_256_f32": lambda: synth.config1(),
     "ragged_300x170_u16": _ragged,
     "min_32x32_f32": lambda: synth.single_ring(32, 32, 15.0, 16.0, 9.3),
     "tail_161x97_f32": _tail,
+    "big_ring_300_f32": _big_ring,
 }
 
 
@@ -146,7 +154,8 @@ def _oracle_ridge_inputs(f):
     return xs, ys, qx, qy, xy, q
 
 
-@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32"])
+@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32",
+                                  "big_ring_300_f32"])
 def test_accumulator_and_scores_bit_exact(det, name):
     say(f"[accumulate] {name}")
     f = _frame(name)
@@ -176,7 +185,8 @@ def _match(ref, got):
     return kr, kg
 
 
-@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32"])
+@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32",
+                                  "big_ring_300_f32"])
 def test_rings_from_oracle_ridges_exact(det, name):
     say(f"[rings from oracle ridges] {name}")
     f = _frame(name)
