@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--diff-frames", type=int, default=16, help="frames of the differentiable step (0: skip)")
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--stream-launches", type=int, default=3, help="32-frame launches of the stream (0: skip)")
-    ap.add_argument("--cpu-frames", type=int, default=6, help="frames of the CPU-oracle sample")
+    ap.add_argument("--cpu-frames", type=int, default=12, help="frames of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-sized device buffer 10 times (reference for HBM byte counters)")

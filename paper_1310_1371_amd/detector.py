@@ -69,6 +69,7 @@ class Detector:
         self.default_tuning = self.get_tuning()
         self.max_peaks = max_peaks
         self._rings = (N.RdRing * max_peaks)()
+        self._batch_buf = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -121,14 +122,17 @@ class Detector:
         n = len(frames)
         arr = self._frame_array(frames)
         cap = capacity_per_frame or self.max_peaks
-        out = (N.RdRing * (n * cap))()
+        # one uninitialised host buffer, kept across calls: only the rings found are written
+        if self._batch_buf is None or self._batch_buf.shape[0] < n * cap:
+            self._batch_buf = np.empty(n * cap, dtype=RING_DTYPE)
+        buf = self._batch_buf
+        out = ctypes.cast(buf.ctypes.data, ctypes.POINTER(N.RdRing))
         offs = (ctypes.c_int64 * n)(*[i * cap for i in range(n)])
         caps = (ctypes.c_int32 * n)(*([cap] * n))
         counts = (ctypes.c_int32 * n)()
         p = N.make_params(params)
         st = self._lib.rd_detect_batch(self._h, arr, n, ctypes.byref(p), out, offs, caps, counts)
         N.check(st, "rd_detect_batch")
-        buf = np.frombuffer(out, dtype=RING_DTYPE)
         return [buf[i * cap:i * cap + counts[i]].copy() for i in range(n)]
 
     def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = None, use_graph: bool = True):
