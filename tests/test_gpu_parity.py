@@ -168,6 +168,27 @@ def test_accumulator_and_scores_bit_exact(det, name):
     np.testing.assert_array_equal(sc.cpu().numpy(), S_ref)
 
 
+def test_dense_ridges_pieces_and_per_level_hotspots(det):
+    """A 120 x 120 block in which every pixel is a ridge with a random direction (14400 ridges,
+    full 16 x 16 bins): each vote tile sees several times more candidate ridges than it stages
+    at once, and with T_int = 0 more hotspots per level chunk than its list holds, so both
+    fallbacks (ridges staged in pieces, hotspots listed level by level) run."""
+    say("[accumulate] dense ridge block, T_int = 0")
+    W = H = 160
+    yy, xx = np.mgrid[20:140, 20:140]
+    xs, ys = xx.ravel().astype(np.int64), yy.ravel().astype(np.int64)
+    th = np.random.default_rng(7).uniform(0.0, 2.0 * np.pi, xs.size)
+    qx = np.rint(16384 * np.cos(th)).astype(np.int64)
+    qy = np.rint(16384 * np.sin(th)).astype(np.int64)
+    p = dict(O.DEFAULTS, **dict(synth.PARAMS_C1, vote_threshold=0, peak_fraction=50.0))
+    _, A_ref, S_ref = O.detect_from_ridges(xs, ys, qx, qy, W, H, p, return_volumes=True)
+    xy = np.stack([xs, ys], 1).astype(np.int32)
+    q = np.stack([qx, qy], 1).astype(np.int16)
+    acc, sc = det.accumulate(xy, q, W, H, p)
+    np.testing.assert_array_equal(acc.cpu().numpy().astype(np.int64), A_ref)
+    np.testing.assert_array_equal(sc.cpu().numpy(), S_ref)
+
+
 def test_accumulator_bit_exact_c2_full(det):
     say("[accumulate] c2 1024x1024, 68 levels")
     f = synth.config2()
