@@ -189,6 +189,22 @@ def test_dense_ridges_pieces_and_per_level_hotspots(det):
     np.testing.assert_array_equal(sc.cpu().numpy(), S_ref)
 
 
+def test_strong_list_overflow_is_reported(det):
+    """The same dense block with every hotspot above the score threshold overflows the per-chunk
+    list of above-threshold voxels: the call reports RD_E_OVERFLOW instead of a wrong answer."""
+    from paper_1310_1371_amd import native as N
+    say("[accumulate] strong-list overflow")
+    yy, xx = np.mgrid[20:140, 20:140]
+    xs, ys = xx.ravel(), yy.ravel()
+    th = np.random.default_rng(7).uniform(0.0, 2.0 * np.pi, xs.size)
+    xy = np.stack([xs, ys], 1).astype(np.int32)
+    q = np.stack([np.rint(16384 * np.cos(th)), np.rint(16384 * np.sin(th))], 1).astype(np.int16)
+    p = dict(O.DEFAULTS, **dict(synth.PARAMS_C1, vote_threshold=0, peak_fraction=0.0))
+    with pytest.raises(N.RdError) as e:
+        det.accumulate(xy, q, 160, 160, p)
+    assert e.value.status == N.RD_E_OVERFLOW
+
+
 def test_accumulator_bit_exact_c2_full(det):
     say("[accumulate] c2 1024x1024, 68 levels")
     f = synth.config2()
