@@ -46,7 +46,8 @@ typedef enum {
     RD_E_DEVICE = 3,     /* no usable gfx950 device, or a HIP runtime error               */
     RD_E_TOO_LARGE = 4,  /* frame or batch larger than the maxima given to rd_create       */
     RD_E_TRUNCATED = 5,  /* output capacity too small; the count written is the required one */
-    RD_E_OVERFLOW = 6    /* an internal list (peaks) exceeded its capacity; result invalid */
+    RD_E_OVERFLOW = 6    /* an internal list (the peaks of a frame, or the above-threshold
+                            voxels of one tile's level chunk) overflowed; result invalid  */
 } rd_status;
 
 typedef enum { RD_U16 = 1, RD_F32 = 2 } rd_dtype;
