@@ -175,7 +175,8 @@ rd_status rd_read_stats(rd_handle h, int64_t* stats6);
 /* ---- kernel timing (measurement) ---------------------------------------------------- */
 
 /* Turn per-kernel timing on (1) or off (0).  When on, detection calls record HIP events on
- * the context's stream around each kernel launch (a small per-launch cost). */
+ * the context's stream around each kernel launch (a small per-launch cost); with graphs in
+ * use the records are nodes of the captured graph, so the timed calls still replay it. */
 rd_status rd_enable_timing(rd_handle h, int32_t enable);
 
 /* Accumulated kernel time since the last reset, per stage: [0] ridge kernel (steps 1-2),

@@ -285,9 +285,11 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
 
 // The pipeline on the frames described in d_frames; results in h_rings / h_counts.
 rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg, int tt, int tv) {
-    const bool graph = h->tune.use_graph && h->stream != nullptr && !h->timing;
+    // with timing on, the events are recorded by nodes of the captured graph
+    const bool graph = h->tune.use_graph && h->stream != nullptr;
     if (graph) {
         GraphKey k;
+        k.timing = h->timing;
         k.nframes = nframes;
         k.dtype = dtype;
         k.rg = rg;

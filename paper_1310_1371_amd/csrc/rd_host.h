@@ -39,10 +39,11 @@ inline bool same_params(const rd_params& a, const rd_params& b) {
 // pointers and sizes live in the device-side descriptor table and may change freely.
 struct GraphKey {
     int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, nchunks = 0, blocks = 0;
+    bool timing = false;   // the graph holds the timing events' record nodes
     size_t lds = 0;
     rd_params params{};
     bool operator==(const GraphKey& o) const {
-        return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant &&
+        return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant && timing == o.timing &&
                total_tiles == o.total_tiles && total_vtiles == o.total_vtiles && nchunks == o.nchunks &&
                blocks == o.blocks && lds == o.lds && same_params(params, o.params);
     }

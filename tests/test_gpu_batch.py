@@ -106,6 +106,24 @@ def test_tuning_invariance(bdet, stencil_tile, vote_lds_kb):
     assert s0 == s1
 
 
+def test_timing_events_inside_the_graph(bdet):
+    """With timing on, the replayed graph carries the event records: every stage is timed on
+    every call, and the rings stay the same with timing on, and after it is turned off."""
+    say("[timing] events as graph nodes")
+    f = synth.config2(seed=78, W=640, H=480, n_rings=80)
+    img = torch.from_numpy(f.image).cuda()
+    bdet.set_tuning(use_graph=True)
+    ref = bdet.detect(img, f.params)
+    bdet.enable_timing(True)
+    bdet.read_timing(reset=True)
+    for _ in range(3):
+        assert _same(ref, bdet.detect(img, f.params))
+    t = bdet.read_timing(reset=True)
+    bdet.enable_timing(False)
+    assert all(n == 3 and ms > 0.0 for ms, n in t.values()), t
+    assert _same(ref, bdet.detect(img, f.params))
+
+
 def test_tuning_beyond_the_lds_limit_is_rejected(bdet):
     """The default is the largest histogram budget; one KiB more is refused on the host."""
     top = bdet.default_tuning["vote_lds_kb"]
