@@ -114,7 +114,7 @@ void stencil_tile_dims(int variant, int rg, bool dense, int* tw, int* th);
 hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, int variant, bool dense, hipStream_t s);
 
 constexpr int VOTE_TILE = 32;
-constexpr int VOTE_LDS_MAX = RD_VOTE_LDS_KB_MAX * 1024;   // dynamic LDS of the vote kernel (static ~91 KB)
+constexpr int VOTE_LDS_MAX = RD_VOTE_LDS_KB_MAX * 1024;   // dynamic LDS of the vote kernel (static ~70 KB)
 constexpr int VOTE_NLEV_MAX = 20;          // accumulator levels per level chunk
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
 hipError_t vote_prepare();   // one-time kernel attributes (outside any graph capture)

@@ -67,7 +67,8 @@ __device__ __forceinline__ uint32_t get_u16(const uint32_t* s, int idx) {
 
 constexpr int LMAX = R_LIMIT + 3;          // levels r_min - 1 .. r_max + 1 at most
 constexpr int NLEV_MAX = VOTE_NLEV_MAX;    // accumulator levels per level chunk
-constexpr int RCAP = 3072;                 // ridge records staged per tile
+constexpr int ACAP = 1536;                 // staged ridges (with a sign that can reach the tile)
+constexpr int PCAP = 160;                  // pieces of the candidate list (rounds of NT candidates)
 constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the per-level fallback)
 constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
 constexpr int WC = K_MAX + 8;              // centre tap of the padded weight row
@@ -90,10 +91,12 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     constexpr int BINS_PER_SIDE = ((T + 2 + 2 * K_MAX + 2 * (R_LIMIT + 2)) >> BIN_SHIFT) + 2;
     static_assert(BINS_PER_SIDE * BINS_PER_SIDE <= NT, "one thread per candidate bin");
     extern __shared__ __align__(16) uint32_t sA[];           // u16 histogram, two per word
-    __shared__ uint32_t sRidXY[RCAP];
-    __shared__ uint32_t sRidQ[RCAP];
-    __shared__ uint32_t sRidR[RCAP];                         // level ranges of both signs (u8 pairs)
-    __shared__ uint16_t sOrd[2 * RCAP];                      // (ridge, sign) items by first level
+    __shared__ uint32_t sRidXY[ACAP];
+    __shared__ uint32_t sRidQ[ACAP];
+    __shared__ uint32_t sRidR[ACAP];                         // level ranges of both signs (u8 pairs)
+    __shared__ uint16_t sOrd[2 * ACAP];                      // (ridge, sign) items by first level
+    __shared__ int32_t sCur[PCAP + 1];                       // first candidate round of each piece
+    __shared__ int32_t sNPieces;
     __shared__ uint32_t sKey[256];                           // counting-sort offsets
     __shared__ uint32_t sNact;                               // items with a non-empty level range
     // hotspot list and scores
@@ -182,8 +185,12 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         const uint32_t pre = block_excl_scan(cnt, sWave, &total);
         sBinPre[tid] = pre;
         sBinId[tid] = bin_local;
-        if (tid == 0) sBinPre[NT] = total;
-        const int npieces = static_cast<int>((total + RCAP - 1) / RCAP);
+        if (tid == 0) {
+            sBinPre[NT] = total;
+            sCur[0] = 0;
+            sNPieces = PCAP + 1;                          // known once the first chunk has staged
+        }
+        const int nrounds = static_cast<int>((total + NT - 1) / NT);
 
         // clear chunk c's histogram, fill its weight rows and empty its hotspot list; chunk 0
         // here, chunk c + 1 during chunk c's 3x3x3 phase, which touches none of these
@@ -224,68 +231,93 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             const int AW = ax1 - ax0, AH = ay1 - ay0;
             const int AWP = (AW + 8) & ~7;                    // 16-byte rows, >= 1 zero column
             const int plane = AWP * AH;                       // u16 per level, multiple of 8
-            // ---- votes of the staged ridges (staged once per tile unless they need pieces)
-            for (int pc = 0; pc < npieces; ++pc) {
-                const uint32_t pbase = static_cast<uint32_t>(pc) * RCAP;
-                const int pn = static_cast<int>(min(total - pbase, static_cast<uint32_t>(RCAP)));
-                if (npieces > 1 || c == 0) {
-                    for (int j = tid; j < pn; j += NT) {
-                        const uint32_t g = pbase + j;
-                        int lo = 0, hi = NT;                      // largest lo with sBinPre[lo] <= g
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (sBinPre[mid] <= g) lo = mid; else hi = mid;
-                        }
-                        const int64_t slot = (fd.bin0 + sBinId[lo]) * BIN_CAP + (g - sBinPre[lo]);
-                        const uint32_t xy = a.rxy[slot], q = a.rq[slot];
-                        sRidXY[j] = xy;
-                        sRidQ[j] = q;
-                        // levels (relative to lbase) at which each sign's vote can land in the
-                        // tile's widest accumulator region: |rho - l q / 2^14| <= 1/2 per axis
-                        const int x = xy & 0xffffu, y = xy >> 16;
-                        const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
-                        uint32_t rr = 0;
+            // ---- votes of the staged ridges.  Only ridges with a sign that can reach the tile
+            // are staged.  They are staged once per tile when they fit (ACAP); otherwise the
+            // first chunk cuts the candidate list into pieces of whole rounds of NT candidates
+            // that fit, and every chunk restages the pieces one after another.
+            for (int pc = 0;; ++pc) {
+                if (c == 0 || sNPieces > 1) {
+                    const int rend = c == 0 ? nrounds : sCur[pc + 1];
+                    uint32_t pn = 0;
+                    int rd = sCur[pc];
+                    for (; rd < rend; ++rd) {
+                        const uint32_t g = static_cast<uint32_t>(rd) * NT + tid;
+                        uint32_t xy = 0, q = 0, rr = 0x00ff00ffu;   // both signs empty
+                        if (g < total) {
+                            int lo = 0, hi = NT;                  // largest lo with sBinPre[lo] <= g
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (sBinPre[mid] <= g) lo = mid; else hi = mid;
+                            }
+                            const int64_t slot = (fd.bin0 + sBinId[lo]) * BIN_CAP + (g - sBinPre[lo]);
+                            xy = a.rxy[slot];
+                            q = a.rq[slot];
+                            // levels (relative to lbase) at which each sign's vote can land in the
+                            // tile's widest accumulator region: |rho - l q / 2^14| <= 1/2 per axis
+                            const int x = xy & 0xffffu, y = xy >> 16;
+                            const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
+                            rr = 0;
 #pragma unroll
-                        for (int sg = 0; sg < 2; ++sg) {
-                            const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
-                            float lo_l = static_cast<float>(r_lo - 1), hi_l = static_cast<float>(r_hi);
-                            bool ok = true;
-                            if (sqx != 0) {
-                                const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
-                                float e0 = (static_cast<float>(ux0 - x) - 0.5f) * inv;
-                                float e1 = (static_cast<float>(ux1 - 1 - x) + 0.5f) * inv;
-                                if (sqx < 0) { const float tt = e0; e0 = e1; e1 = tt; }
-                                lo_l = fmaxf(lo_l, e0);
-                                hi_l = fminf(hi_l, e1);
-                            } else {
-                                ok = x >= ux0 && x < ux1;
+                            for (int sg = 0; sg < 2; ++sg) {
+                                const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
+                                float lo_l = static_cast<float>(r_lo - 1), hi_l = static_cast<float>(r_hi);
+                                bool ok = true;
+                                if (sqx != 0) {
+                                    const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
+                                    float e0 = (static_cast<float>(ux0 - x) - 0.5f) * inv;
+                                    float e1 = (static_cast<float>(ux1 - 1 - x) + 0.5f) * inv;
+                                    if (sqx < 0) { const float tt = e0; e0 = e1; e1 = tt; }
+                                    lo_l = fmaxf(lo_l, e0);
+                                    hi_l = fminf(hi_l, e1);
+                                } else {
+                                    ok = x >= ux0 && x < ux1;
+                                }
+                                if (sqy != 0) {
+                                    const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqy));
+                                    float e0 = (static_cast<float>(uy0 - y) - 0.5f) * inv;
+                                    float e1 = (static_cast<float>(uy1 - 1 - y) + 0.5f) * inv;
+                                    if (sqy < 0) { const float tt = e0; e0 = e1; e1 = tt; }
+                                    lo_l = fmaxf(lo_l, e0);
+                                    hi_l = fminf(hi_l, e1);
+                                } else {
+                                    ok = ok && y >= uy0 && y < uy1;
+                                }
+                                int la = 255, lb = 0;                      // empty
+                                if (ok && lo_l <= hi_l + 2.0f) {
+                                    la = max(r_lo - 1, static_cast<int>(floorf(lo_l)) - 1) - lbase;
+                                    lb = min(r_hi, static_cast<int>(ceilf(hi_l)) + 1) - lbase;
+                                    if (lb < la) { la = 255; lb = 0; }
+                                }
+                                rr |= (static_cast<uint32_t>(la) | (static_cast<uint32_t>(lb) << 8)) << (16 * sg);
                             }
-                            if (sqy != 0) {
-                                const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqy));
-                                float e0 = (static_cast<float>(uy0 - y) - 0.5f) * inv;
-                                float e1 = (static_cast<float>(uy1 - 1 - y) + 0.5f) * inv;
-                                if (sqy < 0) { const float tt = e0; e0 = e1; e1 = tt; }
-                                lo_l = fmaxf(lo_l, e0);
-                                hi_l = fminf(hi_l, e1);
-                            } else {
-                                ok = ok && y >= uy0 && y < uy1;
-                            }
-                            int la = 255, lb = 0;                      // empty
-                            if (ok && lo_l <= hi_l + 2.0f) {
-                                la = max(r_lo - 1, static_cast<int>(floorf(lo_l)) - 1) - lbase;
-                                lb = min(r_hi, static_cast<int>(ceilf(hi_l)) + 1) - lbase;
-                                if (lb < la) { la = 255; lb = 0; }
-                            }
-                            rr |= (static_cast<uint32_t>(la) | (static_cast<uint32_t>(lb) << 8)) << (16 * sg);
                         }
-                        sRidR[j] = rr;
+                        const uint32_t act = ((rr & 0xffu) != 255u || ((rr >> 16) & 0xffu) != 255u) ? 1u : 0u;
+                        uint32_t tot;
+                        const uint32_t off = block_excl_scan(act, sWave, &tot);
+                        if (pn + tot > static_cast<uint32_t>(ACAP)) break;   // first chunk only: the piece ends
+                        if (act) {
+                            sRidXY[pn + off] = xy;
+                            sRidQ[pn + off] = q;
+                            sRidR[pn + off] = rr;
+                        }
+                        pn += tot;
+                        __syncthreads();                          // sWave is rewritten next round
+                    }
+                    if (c == 0 && tid == 0) {
+                        sCur[pc + 1] = rd;
+                        if (rd >= nrounds) {
+                            sNPieces = pc + 1;
+                        } else if (pc + 1 == PCAP) {                  // cannot happen: rounds <= 133
+                            sNPieces = PCAP;
+                            atomicOr(a.error, 1u);
+                        }
                     }
                     for (int i = tid; i < 256; i += NT) sKey[i] = 0u;
                     __syncthreads();
                     // order the (ridge, sign) items whose range meets the tile by first level
                     // (counting sort): the lanes of a wave then run level loops of similar
                     // extent; the items that miss the tile (key 255, most of them) are dropped
-                    for (int it = tid; it < 2 * pn; it += NT) {
+                    for (int it = tid; it < static_cast<int>(2 * pn); it += NT) {
                         const uint32_t key = (sRidR[it >> 1] >> (16 * (it & 1))) & 0xffu;
                         if (key != 255u) atomicAdd(&sKey[key], 1u);   // empty items are not placed
                     }
@@ -308,7 +340,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         }
                     }
                     __syncthreads();
-                    for (int it = tid; it < 2 * pn; it += NT) {
+                    for (int it = tid; it < static_cast<int>(2 * pn); it += NT) {
                         const uint32_t key = (sRidR[it >> 1] >> (16 * (it & 1))) & 0xffu;
                         if (key != 255u) sOrd[atomicAdd(&sKey[key], 1u)] = static_cast<uint16_t>(it);
                     }
@@ -354,6 +386,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     }
                 }
                 __syncthreads();
+                if (pc + 1 >= sNPieces) break;
             }
 
             // ---- hotspots (A > T_int) of the score region: 16-byte loads (eight counters)
