@@ -131,25 +131,29 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sWave, uint
     return base + inc - v;
 }
 
-// Integer level range (superset) over which o + r d stays in [lo, hi).
+// Integer level range (superset) over which o + r d stays in [lo, hi).  Only a superset is
+// needed (every splat is bounds-checked), so fp32 with a reciprocal and one level of margin
+// on each side serves.
 __device__ __forceinline__ void clip_axis(double o, double d, double lo, double hi, int& r0, int& r1) {
-    if (fabs(d) <= 1e-9) {
-        if (o < lo - 1.0 || o > hi) {
+    const float df = static_cast<float>(d);
+    if (fabsf(df) <= 1e-6f) {                  // moves at most (R_LIMIT + 3) 1e-6 px: keep a margin
+        if (o < lo - 1.001 || o > hi + 0.001) {
             r0 = 1;
             r1 = 0;
         }
         return;
     }
-    double t0 = (lo - o) / d, t1 = (hi - o) / d;
+    const float inv = __builtin_amdgcn_rcpf(df);
+    float t0 = static_cast<float>(lo - o) * inv, t1 = static_cast<float>(hi - o) * inv;
     if (t0 > t1) {
-        const double tt = t0;
+        const float tt = t0;
         t0 = t1;
         t1 = tt;
     }
-    t0 = fmax(t0, static_cast<double>(r0) - 1.0);
-    t1 = fmin(t1, static_cast<double>(r1) + 1.0);
-    r0 = max(r0, static_cast<int>(ceil(t0)) - 1);
-    r1 = min(r1, static_cast<int>(floor(t1)) + 1);
+    t0 = fmaxf(t0, static_cast<float>(r0) - 2.0f);
+    t1 = fminf(t1, static_cast<float>(r1) + 2.0f);
+    r0 = max(r0, static_cast<int>(ceilf(t0)) - 2);
+    r1 = min(r1, static_cast<int>(floorf(t1)) + 2);
 }
 
 __global__ __launch_bounds__(NT) void k_soft_fwd(SoftFwdArgs a) {
