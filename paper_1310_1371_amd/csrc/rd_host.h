@@ -89,6 +89,7 @@ struct rd_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
+    uint64_t t_calls = 0;   // timed calls (the ridge and fit kernels are read on every eighth)
     // tuning and the cached level tables
     rd_tuning tune{0, RD_VOTE_LDS_KB_MAX, 1};
     rd_params tab_params{};
