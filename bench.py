@@ -244,9 +244,30 @@ def main():
             det.detect_batch(frames, p)
         torch.cuda.synchronize()
         dtb = (time.perf_counter() - t0) / args.batch_steps
+        # per-kernel times of the batch (timing events in the replayed graph), after the
+        # timed batches; every kernel is read on the first call after a reset
+        det.enable_timing(True)
+        kb = {}
+        for _ in range(2):
+            det.read_timing(reset=True)
+            det.detect_batch(frames, p)
+            for k, (ms, n) in det.read_timing(reset=True).items():
+                kb.setdefault(k, []).append(ms / max(n, 1))
+        det.enable_timing(False)
+        kb = {k: min(v) for k, v in kb.items()}
+        nr_b = det.stats()["ridges"]
+        # the ridge kernel's own figures: 86 fp64 flops per pixel (two 17-tap passes, the
+        # Sobel responses, the eigenvalue), and HBM bytes 2 per u16 pixel read + 12 per ridge
+        st_s = kb["ridge"] * 1e-3
         out["batched"] = {"frames": args.batch, "value": args.batch * px / dtb / 1e6, "unit": "Mpixel/s",
                           "frames_per_s": args.batch / dtb, "ms_per_batch": dtb * 1e3,
                           "vs_plain": (args.batch * px / dtb / 1e6) / value,
+                          "kernel_ms_per_batch": kb,
+                          "ridge_kernel": {"bound": "alu", "achieved": 86.0 * args.batch * px / st_s / 1e12,
+                                           "peak": 78.6, "unit": "TFLOP/s (fp64)",
+                                           "frac": 86.0 * args.batch * px / st_s / 1e12 / 78.6,
+                                           "hbm_GBs": (2.0 * args.batch * px + 12.0 * nr_b) / st_s / 1e9,
+                                           "hbm_frac": (2.0 * args.batch * px + 12.0 * nr_b) / st_s / 8e12},
                           "workload": f"{args.batch} frames of 1024x1024 u16, 200 rings each (seeds 1000..)"}
         del frames
 

@@ -92,7 +92,7 @@ struct StencilShape {
     static constexpr int KW = TW + 2, KH = TH + 2; // k_- region (tile + 1 px)
     static constexpr int MH = 10;                  // outputs per thread, horizontal pass
     static constexpr int MV = 13;                  // vertical pass
-    static constexpr int MS = 12;                  // Sobel/eigen pass
+    static constexpr int MS = 6;                   // Sobel/eigen pass
     static constexpr int NBX = TW / BIN, NBY = TH / BIN;
     static constexpr int SZ_I = IH * IWP * 4;
     static constexpr int SZ_G = GH * HC * 8;
@@ -139,12 +139,33 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
         const int x0 = (local % tiles_x) * TW;
         const int y0 = (local / tiles_x) * TH;
 
-        // ---- load the input tile with mirrored borders
-        for (int i = tid; i < IH * IW; i += NT) {
-            const int r = i / IW, c = i - r * IW;
-            const int gy = reflect101(y0 - HALO + r, H);
-            const int gx = reflect101(x0 - HALO + c, W);
-            sI[r * IWP + c] = load_px<TIN>(fd.img, fd.pitch, gx, gy);
+        // ---- load the input tile with mirrored borders: a thread's loads are issued in groups
+        // of eight before any of them is stored, so their latencies overlap
+        {
+            constexpr int NLD = (IH * IW + NT - 1) / NT, G = 8;
+#pragma unroll
+            for (int k0 = 0; k0 < NLD; k0 += G) {
+                float v[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int i = tid + (k0 + k) * NT;
+                    v[k] = 0.0f;
+                    if (k0 + k < NLD && i < IH * IW) {
+                        const int r = i / IW, c = i - r * IW;
+                        const int gy = reflect101(y0 - HALO + r, H);
+                        const int gx = reflect101(x0 - HALO + c, W);
+                        v[k] = load_px<TIN>(fd.img, fd.pitch, gx, gy);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int i = tid + (k0 + k) * NT;
+                    if (k0 + k < NLD && i < IH * IW) {
+                        const int r = i / IW, c = i - r * IW;
+                        sI[r * IWP + c] = v[k];
+                    }
+                }
+            }
         }
         __syncthreads();
 
