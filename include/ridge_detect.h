@@ -145,7 +145,7 @@ rd_status rd_detect_batch(rd_handle h, const rd_frame* frames, int32_t n, const 
                           int32_t* n_rings);
 
 /* Largest vote_lds_kb: what the vote kernel's own LDS leaves of a compute unit's 160 KiB. */
-#define RD_VOTE_LDS_KB_MAX 90
+#define RD_VOTE_LDS_KB_MAX 89
 
 /* Launch configuration choices.  None changes any result.  A new context starts at
  * {0, RD_VOTE_LDS_KB_MAX, 1}. */

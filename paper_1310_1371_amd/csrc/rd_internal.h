@@ -33,6 +33,8 @@ struct FrameDesc {
     int32_t pad;
 };
 
+constexpr int FRAMES_LDS = 64;   // frame tables up to this size are read into LDS by the kernels
+
 struct Peak {
     int32_t a, b, r, frame;
     uint64_t s;          // integer smoothed score S_int

@@ -117,6 +117,8 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
 
     __shared__ __align__(16) uint8_t smem[SH::LDS];
     __shared__ uint32_t wcount[NB][NT / 64];
+    // the frame table of a launch of up to FRAMES_LDS frames, read once per workgroup
+    __shared__ FrameDesc sFr[FRAMES_LDS];
     float* sI = reinterpret_cast<float*>(smem);                 // region A
     double* sG = reinterpret_cast<double*>(smem);               // region A (after sI dies)
     double* sH = reinterpret_cast<double*>(smem + SH::SZ_A);    // region B
@@ -128,21 +130,30 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
     const int wave = tid >> 6;
     const double kthr = a.k_threshold;
 
+    const bool fr_lds = a.nframes <= FRAMES_LDS;
+    if (fr_lds) {
+        for (int i = tid; i < a.nframes; i += NT) sFr[i] = a.frames[i];
+        __syncthreads();
+    }
+
     for (int t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
         // ---- which frame / tile
-        int f = 0;
-        while (f + 1 < a.nframes && a.frames[f + 1].tile0 <= t) ++f;
-        const FrameDesc fd = a.frames[f];
+        int f = 0;                                  // last frame whose first tile is <= t
+        for (int hi = a.nframes; hi - f > 1;) {
+            const int mid = (f + hi) >> 1;
+            if ((fr_lds ? sFr[mid].tile0 : a.frames[mid].tile0) <= t) f = mid; else hi = mid;
+        }
+        const FrameDesc fd = fr_lds ? sFr[f] : a.frames[f];
         const int W = fd.W, H = fd.H;
         const int tiles_x = (W + TW - 1) / TW;
         const int local = t - fd.tile0;
         const int x0 = (local % tiles_x) * TW;
         const int y0 = (local / tiles_x) * TH;
 
-        // ---- load the input tile with mirrored borders: a thread's loads are issued in groups
-        // of eight before any of them is stored, so their latencies overlap
+        // ---- load the input tile with mirrored borders: a thread's loads (up to twenty at a
+        // time) are all issued before any of them is stored, so their latencies overlap
         {
-            constexpr int NLD = (IH * IW + NT - 1) / NT, G = 8;
+            constexpr int NLD = (IH * IW + NT - 1) / NT, G = NLD < 20 ? NLD : 20;
 #pragma unroll
             for (int k0 = 0; k0 < NLD; k0 += G) {
                 float v[G];

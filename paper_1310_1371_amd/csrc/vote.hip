@@ -96,6 +96,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ uint32_t sRidR[ACAP];                         // level ranges of both signs (u8 pairs)
     __shared__ uint16_t sOrd[2 * ACAP];                      // (ridge, sign) items by first level
     __shared__ int32_t sCur[PCAP + 1];                       // first candidate round of each piece
+    __shared__ int32_t sVt0[FRAMES_LDS];                     // first vote tile of each frame
     __shared__ int32_t sNPieces;
     __shared__ uint32_t sKey[256];                           // counting-sort offsets
     __shared__ uint32_t sNact;                               // items with a non-empty level range
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     // pairs starting at even (sWpE) and odd (sWpO) taps, for two-tap dot products
     __shared__ uint32_t sWpE[NLEV_MAX][NWW];
     __shared__ uint32_t sWpO[NLEV_MAX][NWW];
-    __shared__ int sTile;
+    __shared__ int sTile, sFrame;
     __shared__ unsigned long long sThr[LMAX];
     __shared__ int32_t sKt[LMAX];
     __shared__ int32_t sChunk[LMAX + 1];
@@ -132,6 +133,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         sKt[i] = a.ktab[i];
     }
     for (int i = tid; i <= a.nchunks; i += NT) sChunk[i] = a.chunk_start[i];
+    if (a.nframes <= FRAMES_LDS)
+        for (int i = tid; i < a.nframes; i += NT) sVt0[i] = a.frames[i].vtile0;
     __syncthreads();
 
     const int lbase = a.lbase;
@@ -142,12 +145,20 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
 
     for (;;) {
         // tiles are taken from a queue: their cost varies with the number of hotspots
-        if (tid == 0) sTile = static_cast<int>(atomicAdd(a.tile_counter, 1u));
+        if (tid == 0) {
+            const int tq = static_cast<int>(atomicAdd(a.tile_counter, 1u));
+            int fq = 0;                             // last frame whose first vote tile is <= tq
+            for (int hi = a.nframes; hi - fq > 1;) {
+                const int mid = (fq + hi) >> 1;
+                if ((a.nframes <= FRAMES_LDS ? sVt0[mid] : a.frames[mid].vtile0) <= tq) fq = mid; else hi = mid;
+            }
+            sTile = tq;
+            sFrame = fq;
+        }
         __syncthreads();
         const int t = sTile;
         if (t >= a.total_vtiles) break;
-        int f = 0;
-        while (f + 1 < a.nframes && a.frames[f + 1].vtile0 <= t) ++f;
+        const int f = sFrame;
         const FrameDesc fd = a.frames[f];
         const int W = fd.W, H = fd.H;
         const int tiles_x = (W + T - 1) / T;
