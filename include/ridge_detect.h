@@ -181,9 +181,8 @@ rd_status rd_enable_timing(rd_handle h, int32_t enable);
 
 /* Accumulated kernel time since the last reset, per stage: [0] ridge kernel (steps 1-2),
  * [1] vote/smooth/peak kernel (steps 3-4), [2] fit kernel (step 5); ms_total[i] in
- * milliseconds and launches[i] the number of launches timed.  The vote kernel is timed on
- * every call, the ridge and fit kernels on the first call after a reset and every eighth
- * after it.  reset != 0 clears them. */
+ * milliseconds and launches[i] the number of launches timed: the first call after a reset
+ * and every eighth call after it are timed.  reset != 0 clears them. */
 rd_status rd_read_timing(rd_handle h, double* ms_total, int64_t* launches, int32_t reset);
 
 /* ---- stage entry points (parity checks; same kernels as rd_detect) ------------------- */

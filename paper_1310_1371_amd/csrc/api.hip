@@ -243,22 +243,19 @@ FitArgs fit_args(rd_ctx* h, const rd_params& p, int nframes, rd_ring* rings, uin
 }
 
 rd_status mark(rd_ctx* h, int i) {
-    if (h->timing) RD_HIP(hipEventRecord(h->ev[i], h->stream));
+    if (h->mark_now) RD_HIP(hipEventRecord(h->ev[i], h->stream));
     return RD_OK;
 }
 
-// After the stream has been synchronised: add the elapsed times between the marks.  The
-// vote kernel's time is read on every call; the ridge and fit kernels' on every eighth (each
-// read of an event pair is a runtime query of its own, a cost the timed calls should not
-// carry three times over).
+// After the stream has been synchronised: add the elapsed times between the marks of a call
+// that recorded them.
 void collect_timing(rd_ctx* h, bool with_stencil) {
-    if (!h->timing) return;
+    if (!h->mark_now) return;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev[1], h->ev[2]) == hipSuccess) {
         h->t_ms[1] += ms;
         h->t_n[1] += 1;
     }
-    if ((h->t_calls++ & 7) != 0) return;
     if (with_stencil && hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess) {
         h->t_ms[0] += ms;
         h->t_n[0] += 1;
@@ -289,11 +286,15 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
 
 // The pipeline on the frames described in d_frames; results in h_rings / h_counts.
 rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg, int tt, int tv) {
-    // with timing on, the events are recorded by nodes of the captured graph
+    // With timing on, the first call after a reset and every eighth after it record the events;
+    // they replay a second graph that holds the event records, the other calls the plain one
+    // (event records cost the replay a few microseconds each).
+    h->mark_now = h->timing && (h->t_calls++ & 7) == 0;
+    const int gi = h->mark_now ? 1 : 0;
     const bool graph = h->tune.use_graph && h->stream != nullptr;
     if (graph) {
         GraphKey k;
-        k.timing = h->timing;
+        k.timing = h->mark_now;
         k.nframes = nframes;
         k.dtype = dtype;
         k.rg = rg;
@@ -304,10 +305,10 @@ rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, in
         k.blocks = h->cus;
         k.lds = h->tabs.lds;
         k.params = p;
-        if (!h->gexec || !(k == h->gkey)) {
-            if (h->gexec) {
-                (void)hipGraphExecDestroy(h->gexec);
-                h->gexec = nullptr;
+        if (!h->gexec[gi] || !(k == h->gkey[gi])) {
+            if (h->gexec[gi]) {
+                (void)hipGraphExecDestroy(h->gexec[gi]);
+                h->gexec[gi] = nullptr;
             }
             hipGraph_t g = nullptr;
             RD_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -315,23 +316,26 @@ rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, in
             const hipError_t e = hipStreamEndCapture(h->stream, &g);
             if (st != RD_OK || e != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
+                h->mark_now = false;
                 return st != RD_OK ? st : RD_E_DEVICE;
             }
-            const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+            const hipError_t ei = hipGraphInstantiate(&h->gexec[gi], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (ei != hipSuccess) {
-                h->gexec = nullptr;
+                h->gexec[gi] = nullptr;
+                h->mark_now = false;
                 return RD_E_DEVICE;
             }
-            h->gkey = k;
+            h->gkey[gi] = k;
         }
-        RD_HIP(hipGraphLaunch(h->gexec, h->stream));
+        RD_HIP(hipGraphLaunch(h->gexec[gi], h->stream));
     } else {
         RD_TRY(enqueue(h, p, nframes, dtype, rg, true, tt, tv, h->dh_rings, h->dh_counts));
     }
     RD_HIP(hipMemcpyAsync(h->h_stats, h->d_stats, NSTATS * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     collect_timing(h, true);
+    h->mark_now = false;
     return RD_OK;
 }
 
@@ -547,7 +551,8 @@ void rd_destroy(rd_handle h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    for (hipGraphExec_t& g : h->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     soft_state_free(h->soft);
     (void)hipFree(h->d_stage);
     (void)hipFree(h->d_rxy);
@@ -748,10 +753,17 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
     if (!n_rings || capacity < 0 || (capacity > 0 && !out)) return RD_E_INVALID;
     *n_rings = 0;
     RD_TRY(ridge_setup(h, xy_dev, q_dev, n, width, height, params));
-    RD_TRY(enqueue(h, *params, 1, RD_F32, 0, false, 0, vote_tiles(width, height), h->dh_rings, h->dh_counts));
+    h->mark_now = h->timing;                       // every call of this entry point is timed
+    const rd_status st = enqueue(h, *params, 1, RD_F32, 0, false, 0, vote_tiles(width, height), h->dh_rings,
+                                 h->dh_counts);
+    if (st != RD_OK) {
+        h->mark_now = false;
+        return st;
+    }
     RD_HIP(hipMemcpyAsync(h->h_stats, h->d_stats, NSTATS * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     collect_timing(h, false);
+    h->mark_now = false;
     record_stats(h, 1);
     if (h->h_counts[1]) return RD_E_OVERFLOW;
     return copy_rings(h, 0, out, capacity, n_rings);

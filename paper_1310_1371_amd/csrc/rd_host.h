@@ -89,7 +89,7 @@ struct rd_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
-    uint64_t t_calls = 0;   // timed calls (the ridge and fit kernels are read on every eighth)
+    uint64_t t_calls = 0;   // detection calls with timing on since the last reset (every eighth is timed)
     // tuning and the cached level tables
     rd_tuning tune{0, RD_VOTE_LDS_KB_MAX, 1};
     rd_params tab_params{};
@@ -97,8 +97,9 @@ struct rd_ctx {
     bool tab_valid = false;
     rd::LevelTables tabs;
     // captured launch sequence
-    hipGraphExec_t gexec = nullptr;
-    rd::GraphKey gkey;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // [1]: the graph with the timing events
+    rd::GraphKey gkey[2];
+    bool mark_now = false;                          // this call records the timing events
     int64_t last_stats[6] = {0, 0, 0, 0, 0, 0};
     // differentiable path
     rd::SoftState* soft = nullptr;

@@ -120,8 +120,8 @@ def test_timing_events_inside_the_graph(bdet):
         assert _same(ref, bdet.detect(img, f.params))
     t = bdet.read_timing(reset=True)
     bdet.enable_timing(False)
-    # the vote kernel is timed on every call, the others on the first of every eight
-    assert t["vote"][1] == 3 and t["ridge"][1] == 1 and t["fit"][1] == 1, t
+    # the first call of every eight is timed
+    assert all(n == 1 for _, n in t.values()), t
     assert all(ms > 0.0 for ms, _ in t.values()), t
     assert _same(ref, bdet.detect(img, f.params))
 
