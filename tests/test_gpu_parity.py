@@ -277,6 +277,34 @@ def test_end_to_end_rings(det, name):
     assert unmatched <= max(1, 0.01 * len(ref))
 
 
+def test_wide_frame_beyond_2048_columns():
+    """A 5000 x 48 float32 strip (coordinates past 4095 in the packed 16-bit ridge records),
+    with rings along it: accumulator and scores bit-exact from the oracle's ridges, and the
+    end-to-end rings within tolerance."""
+    from paper_1310_1371_amd.detector import Detector
+    say("[wide] 5000 x 48")
+    W, H = 5000, 48
+    cx = np.array([30.0, 1800.5, 4100.2, 4978.0])
+    cy = np.array([24.0, 20.5, 26.0, 23.0])
+    R = np.array([14.0, 18.0, 12.5, 16.0])
+    s_, A = np.full(4, 1.5), np.ones(4)
+    img = synth.render(W, H, np.full((H, W), 0.2), cx, cy, R, s_, A).astype(np.float32)
+    f = synth.Frame(img, cx, cy, R, s_, A, dict(synth.PARAMS_C1), 0)
+    d = Detector(max_width=W, max_height=64, max_peaks=4096)
+    try:
+        p = dict(O.DEFAULTS, **f.params)
+        xs, ys, qx, qy, xy, q = _oracle_ridge_inputs(f)
+        _, A_ref, S_ref = O.detect_from_ridges(xs, ys, qx, qy, W, H, p, return_volumes=True)
+        acc, sc = d.accumulate(xy, q, W, H, p)
+        np.testing.assert_array_equal(acc.cpu().numpy().astype(np.int64), A_ref)
+        np.testing.assert_array_equal(sc.cpu().numpy(), S_ref)
+        ref, got, n_common, unmatched = _end_to_end(d, f, torch.from_numpy(f.image).cuda())
+        say(f"  oracle {len(ref)} gpu {len(got)} matched {n_common} unmatched {unmatched}")
+        assert len(ref) >= 3 and unmatched <= 1
+    finally:
+        d.close()
+
+
 def test_end_to_end_c2_full(det):
     say("[detect] c2 1024x1024 u16")
     f = synth.config2()
