@@ -360,14 +360,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 // votes: each staged ridge and sign over its level range, clipped to this chunk;
                 // the region test below rejects the few votes that land in the tile's widest
                 // region but outside this chunk's
+                // two lanes per item, each over half of its levels in this chunk: more waves
+                // share the loop when fewer items than threads are active
                 const int nact = static_cast<int>(sNact);
-                for (int k = tid; k < nact; k += NT) {
-                    const int it = sOrd[k];
+                for (int k = tid; k < 2 * nact; k += NT) {
+                    const int it = sOrd[k >> 1];
                     const int jr = it >> 1, sg = it & 1;
                     const uint32_t rr = sRidR[jr] >> (16 * sg);
                     const int la_raw = static_cast<int>(rr & 0xffu) + lbase;
                     if (la_raw > l1) break;                       // the rest start later still
-                    const int la = max(la_raw, l0), lb = min(static_cast<int>((rr >> 8) & 0xffu) + lbase, l1);
+                    const int la0 = max(la_raw, l0), lb0 = min(static_cast<int>((rr >> 8) & 0xffu) + lbase, l1);
+                    const int mid = (la0 + lb0) >> 1;
+                    const int la = (k & 1) ? mid + 1 : la0, lb = (k & 1) ? lb0 : mid;
                     if (la > lb) continue;
                     const uint32_t xy = sRidXY[jr], q = sRidQ[jr];
                     const int x = (xy & 0xffffu) - ax0, y = (xy >> 16) - ay0;
