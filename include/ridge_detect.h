@@ -167,9 +167,10 @@ rd_status rd_autotune(rd_handle h, const rd_frame* frames, int32_t n, const rd_p
                       int32_t reps, rd_tuning* best);
 
 /* Counters of the last detection call (any entry point that ran the vote kernel):
- * [0] ridge pixels, [1] votes cast into the frame, [2] hotspots (A > T_int, counted once
- * per level chunk that scores them), [3] smoothing taps evaluated, [4] above-threshold
- * voxels, [5] peaks. */
+ * [0] ridge pixels, [1] vote increments made in the per-tile histograms (a vote within the
+ * smoothing margin of a tile border is made in every tile region that holds it), [2]
+ * hotspots (A > T_int, counted once per level chunk that scores them), [3] smoothing taps
+ * evaluated, [4] above-threshold voxels, [5] peaks. */
 rd_status rd_read_stats(rd_handle h, int64_t* stats6);
 
 /* ---- kernel timing (measurement) ---------------------------------------------------- */
