@@ -357,11 +357,10 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     }
                     __syncthreads();
                 }
-                // votes: each staged ridge and sign over its level range, clipped to this chunk;
-                // the region test below rejects the few votes that land in the tile's widest
-                // region but outside this chunk's
-                // two lanes per item, each over half of its levels in this chunk: more waves
-                // share the loop when fewer items than threads are active
+                // votes: each staged (ridge, sign) item over its level range clipped to this
+                // chunk, split between two lanes (half of the levels each), which spreads the
+                // loop over more waves; the region test below rejects the votes that land in
+                // the tile's widest region but outside this chunk's
                 const int nact = static_cast<int>(sNact);
                 for (int k = tid; k < 2 * nact; k += NT) {
                     const int it = sOrd[k >> 1];
