@@ -10,7 +10,8 @@
 //   1. clears a u16 histogram of those levels in LDS (two counters per 32-bit word);
 //   2. adds every item's votes over its level range with LDS atomics (exact integers: the
 //      direction is the fixed-point code, offset floor((r q + 2^13) / 2^14));
-//   3. lists the hotspots (A > T_int) of the tile + 1 px with 16-byte scans;
+//   3. lists the hotspots (A > T_int) of the tile + 1 px as they arise: the atomic returns
+//      the counter's old value, and the vote that lifts it past T_int lists the voxel;
 //   4. evaluates the integer score S_int = sum W(|dx|) W(|dy|) A of each hotspot with 15-bit
 //      weight factors, in tasks of one 8-column band of the window and half its rows, and
 //      keeps the scores above the level's integer threshold in a "strong" list;
@@ -242,6 +243,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             const int AW = ax1 - ax0, AH = ay1 - ay0;
             const int AWP = (AW + 8) & ~7;                    // 16-byte rows, >= 1 zero column
             const int plane = AWP * AH;                       // u16 per level, multiple of 8
+            // the score region (tile + 1 px) in histogram coordinates
+            const int hu0 = sx0 - ax0, hw = sx1 - sx0, hv0 = sy0 - ay0, hh = sy1 - sy0;
+            if (tid == 0) sNs = 0;                            // last read by the previous 3x3x3 phase
             // ---- votes of the staged ridges.  Only ridges with a sign that can reach the tile
             // are staged.  They are staged once per tile when they fit (ACAP); otherwise the
             // first chunk cuts the candidate list into pieces of whole rounds of NT candidates
@@ -391,8 +395,21 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         if (static_cast<unsigned>(u2) < static_cast<unsigned>(AW2) &&
                             static_cast<unsigned>(v) < static_cast<unsigned>(AH)) {
                             const int b = base + static_cast<int>(__umul24(v, AWP2)) + u2;   // 0 <= v < AH
-                            atomicAdd(&sA[b >> 2], 1u << ((b & 2) << 3));
+                            const int sh = (b & 2) << 3;
+                            const uint32_t old = (atomicAdd(&sA[b >> 2], 1u << sh) >> sh) & 0xffffu;
                             ++st_votes;
+                            // the vote that lifts a counter past T_int lists the voxel as a hotspot,
+                            // once, if it lies in the score region (the tile grown by 1 px)
+                            const int u = u2 >> 1;
+                            if (old == tint && static_cast<unsigned>(u - hu0) < static_cast<unsigned>(hw) &&
+                                static_cast<unsigned>(v - hv0) < static_cast<unsigned>(hh)) {
+                                const uint32_t h = atomicAdd(&sNh, 1u);
+                                if (h < static_cast<uint32_t>(HCAP)) {
+                                    sHot[h] = (static_cast<uint32_t>(l - l0) << 16) |
+                                              static_cast<uint32_t>((v - hv0 + sy0 - (y0 - 1)) * SR + (u - hu0 + sx0 - (x0 - 1)));
+                                    sHS[h] = 0ull;
+                                }
+                            }
                         }
                         accx += sqx;
                         accy += sqy;
@@ -403,49 +420,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 if (pc + 1 >= sNPieces) break;
             }
 
-            // ---- hotspots (A > T_int) of the score region: 16-byte loads (eight counters)
-            // over whole accumulator rows, flattened over (level, row, 16-byte column)
             const int SHh = sy1 - sy0;
-            if (tid == 0) sNs = 0;                            // last read by the previous 3x3x3 phase
-            {
-                const int c8lo = (sx0 - ax0) >> 3, n8 = ((sx1 - 1 - ax0) >> 3) - c8lo + 1;   // 16-byte columns
-                const int rows = nlev * SHh;
-                const uint32_t units = static_cast<uint32_t>(rows * n8);
-                const uint32_t m8 = 0xffffffffu / static_cast<uint32_t>(n8) + 1u;
-                const uint32_t mS = 0xffffffffu / static_cast<uint32_t>(SHh) + 1u;
-                const uint4* a4 = reinterpret_cast<const uint4*>(sA);
-                for (uint32_t u = tid; u < units; u += NT) {
-                    const uint32_t rl = div_mulhi(u, n8, m8), c8 = u - rl * n8 + c8lo;
-                    const uint32_t li = div_mulhi(rl, SHh, mS), r = rl - li * SHh;
-                    const int vy = sy0 + static_cast<int>(r);
-                    const uint4 w4 = a4[((li * plane + (vy - ay0) * AWP) >> 3) + c8];
-                    // largest of the eight counters by packed 16-bit maxima first
-                    const ushort2_t m2 = __builtin_elementwise_max(
-                        __builtin_elementwise_max(__builtin_bit_cast(ushort2_t, w4.x), __builtin_bit_cast(ushort2_t, w4.y)),
-                        __builtin_elementwise_max(__builtin_bit_cast(ushort2_t, w4.z), __builtin_bit_cast(ushort2_t, w4.w)));
-                    if (static_cast<uint32_t>(m2.x > m2.y ? m2.x : m2.y) <= tint) continue;
-                    const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
-                    uint32_t hotmask = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        hotmask |= ((ws[k] & 0xffffu) > tint ? 1u : 0u) << (2 * k);
-                        hotmask |= ((ws[k] >> 16) > tint ? 1u : 0u) << (2 * k + 1);
-                    }
-                    while (hotmask) {
-                        const int k = __ffs(hotmask) - 1;
-                        hotmask &= hotmask - 1;
-                        const int vx = ax0 + static_cast<int>(c8) * 8 + k;
-                        if (vx >= sx0 && vx < sx1) {
-                            const uint32_t h = atomicAdd(&sNh, 1u);
-                            if (h < static_cast<uint32_t>(HCAP)) {
-                                sHot[h] = (li << 16) | static_cast<uint32_t>((vy - (y0 - 1)) * SR + (vx - (x0 - 1)));
-                                sHS[h] = 0ull;
-                            }
-                        }
-                    }
-                }
-            }
-            __syncthreads();
 
             if (DUMP) {
                 const int ix1 = min(x0 + T, W), iy1 = min(y0 + T, H);
