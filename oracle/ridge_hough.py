@@ -8,8 +8,8 @@ What it computes is the dense, array-based formulation of the method (the "convo
 array based" version the paper first wrote, Results, "Key algorithmic optimisations"),
 which the paper's memory-recycling / hotspot machinery reproduces exactly at lower cost.
 All floating point is float64.  Every stage is a function of its own, citing the passage it
-follows.  Readings taken where the paper is silent are marked READING and listed in
-DESIGN.md.
+follows.  Readings taken where the paper is silent are marked READING at the place they
+are taken, with the reason.
 
 Coordinates: x = column, y = row, pixel centres at integers, (0, 0) top-left.
 """

@@ -14,8 +14,8 @@ below 2e-8 of the amplitude.
 
 The workload recipes follow the problem statement of the paper (Results, "Problem
 statement": an image of rings whose centres and radii are wanted) with the sizes and
-distributions listed in the design doc.  The paper's own images are not available, so these
-synthetic frames stand in for them.
+distributions given in each recipe's docstring.  The paper's own images are not available,
+so these synthetic frames stand in for them.
 """
 from __future__ import annotations
 
@@ -25,8 +25,8 @@ import math
 import numpy as np
 
 # ----------------------------------------------------------------------------------------
-# default detection parameters per workload (plain numbers, chosen as documented in
-# curvature threshold at a quarter of the weakest ring's smoothed curvature)
+# default detection parameters per workload (plain numbers: the curvature threshold sits at
+# a quarter of the weakest ring's smoothed curvature)
 # ----------------------------------------------------------------------------------------
 PARAMS_C1 = dict(sigma_smooth=2.0, k_threshold=-0.02, r_min=8, r_max=40, vote_threshold=3,
                  peak_fraction=0.4, sig_slope=0.05, sig_icpt=0.25, annulus_halfwidth=2,
