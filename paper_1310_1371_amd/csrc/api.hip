@@ -352,19 +352,13 @@ void record_stats(rd_ctx* h, int nframes) {
     h->last_stats[5] = peaks;
 }
 
-bool ring_less(const rd_ring& x, const rd_ring& y) {
-    if (x.r_bin != y.r_bin) return x.r_bin < y.r_bin;
-    if (x.b != y.b) return x.b < y.b;
-    return x.a < y.a;
-}
-
-// Sorts frame f's rings in the pinned buffer and copies them out.
+// Copies frame f's rings out of the pinned buffer (the fit kernel wrote them in (r_bin, b, a)
+// order).
 rd_status copy_rings(rd_ctx* h, int f, rd_ring* out, int32_t capacity, int32_t* n_rings) {
     const uint32_t np = h->h_counts[f];
     *n_rings = static_cast<int32_t>(np);
     if (np > static_cast<uint32_t>(h->max_peaks)) return RD_E_OVERFLOW;
-    rd_ring* src = h->h_rings + static_cast<int64_t>(f) * h->max_peaks;
-    std::sort(src, src + np, ring_less);
+    const rd_ring* src = h->h_rings + static_cast<int64_t>(f) * h->max_peaks;
     const uint32_t ncopy = std::min<uint32_t>(np, static_cast<uint32_t>(std::max(capacity, 0)));
     if (ncopy) std::memcpy(out, src, ncopy * sizeof(rd_ring));
     return np > ncopy ? RD_E_TRUNCATED : RD_OK;

@@ -4,7 +4,9 @@
 // annulus' bounding box, takes the ridge pixels with (max(r-w,0))^2 <= (x-a)^2 + (y-b)^2
 // <= (r+w)^2 (an exact integer test; a ridge pixel may belong to several peaks), sums the
 // nine normal-equation moments of the algebraic (Kasa) fit exactly in int64, and one thread
-// solves the 3x3 system in fp64.
+// solves the 3x3 system in fp64.  The workgroup also counts the frame's peaks that precede
+// its own in (r, b, a) order and writes the ring at that rank: peaks are distinct voxels, so
+// the ranks are a permutation and every frame's ring list comes out sorted.
 #include "rd_internal.h"
 
 namespace rd {
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(FNT) void k_fit(FitArgs a) {
     __shared__ uint32_t sPre[FNT + 1];
     __shared__ int64_t sBinBase[FNT];
     __shared__ uint32_t sWave[FNT / 64];
-    __shared__ int64_t sMom[FNT / 64][9];
+    __shared__ int64_t sMom[FNT / 64][10];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (blockIdx.x == 0 && tid == 0 && a.counts_out) {
         for (int f = 0; f < a.nframes; ++f) a.counts_out[f] = a.peak_count[f];
@@ -92,7 +94,12 @@ __global__ __launch_bounds__(FNT) void k_fit(FitArgs a) {
             const int64_t ro2 = static_cast<int64_t>(ro) * ro, ri2 = static_cast<int64_t>(ri) * ri;
             const int bxlo = max((pa - ro) >> BIN_SHIFT, 0), bxhi = min((pa + ro) >> BIN_SHIFT, fd.nbx - 1);
             const int bylo = max((pb - ro) >> BIN_SHIFT, 0), byhi = min((pb + ro) >> BIN_SHIFT, fd.nby - 1);
-            int64_t m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // n, su, sv, suu, suv, svv, sz, suz, svz
+            // n, su, sv, suu, suv, svv, sz, suz, svz, and the rank of the peak in its frame
+            int64_t m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (uint32_t q = tid; q < np; q += FNT) {
+                const Peak o = a.peaks[fd.peak0 + q];
+                m[9] += (o.r < r || (o.r == r && (o.b < pb || (o.b == pb && o.a < pa)))) ? 1 : 0;
+            }
             const int nbxr = bxhi - bxlo + 1;
             const int nbin = nbxr * (byhi - bylo + 1);
             for (int b0 = 0; b0 < nbin; b0 += FNT) {       // rounds of up to FNT bins
@@ -128,14 +135,14 @@ __global__ __launch_bounds__(FNT) void k_fit(FitArgs a) {
                 __syncthreads();                              // sPre is rewritten next round
             }
 #pragma unroll
-            for (int i = 0; i < 9; ++i) m[i] = wave_sum64(m[i]);
+            for (int i = 0; i < 10; ++i) m[i] = wave_sum64(m[i]);
             if (lane == 0)
 #pragma unroll
-                for (int i = 0; i < 9; ++i) sMom[wave][i] = m[i];
+                for (int i = 0; i < 10; ++i) sMom[wave][i] = m[i];
             __syncthreads();
             if (tid == 0) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
+                for (int i = 0; i < 10; ++i) {
                     m[i] = sMom[0][i];
                     for (int w = 1; w < FNT / 64; ++w) m[i] += sMom[w][i];
                 }
@@ -168,7 +175,7 @@ __global__ __launch_bounds__(FNT) void k_fit(FitArgs a) {
                 ring.a = pa; ring.b = pb; ring.r_bin = r;
                 ring.n_fit = static_cast<int32_t>(n);
                 ring.fit_ok = ok;
-                a.rings[fd.peak0 + p] = ring;
+                a.rings[fd.peak0 + m[9]] = ring;    // 0 <= rank < np
             }
             __syncthreads();                                  // sMom is rewritten by the next peak
         }

@@ -51,6 +51,16 @@ def test_batch_equals_per_frame(bdet):
         say(f"  {f.image.shape}: {len(got)} rings")
 
 
+def test_rings_come_out_sorted(bdet):
+    say("[batch] every frame's rings in strictly ascending (r_bin, b, a) order")
+    fs = _frames_u16()
+    frames = [torch.from_numpy(f.image).cuda() for f in fs]
+    for rings in bdet.detect_batch(frames, fs[0].params):
+        keys = [(int(r["r_bin"]), int(r["b"]), int(r["a"])) for r in rings]
+        assert len(keys) > 10
+        assert all(k0 < k1 for k0, k1 in zip(keys, keys[1:]))
+
+
 def test_batch_graph_replay_uses_new_data(bdet):
     say("[batch] graph replay with new frame contents")
     bdet.set_tuning(use_graph=True)
