@@ -114,7 +114,12 @@ rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int var
         bins += static_cast<int64_t>(fd.nbx) * fd.nby;
     }
     if (bins > h->max_bins) return RD_E_TOO_LARGE;
-    RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, n * sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
+    // a call on the same frame buffers (the usual loop) finds its descriptors already there
+    if (h->frames_dev_n != n || std::memcmp(h->frames_dev.data(), h->h_frames, n * sizeof(FrameDesc)) != 0) {
+        RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, n * sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
+        h->frames_dev.assign(h->h_frames, h->h_frames + n);
+        h->frames_dev_n = n;
+    }
     *total_tiles = tt;
     *total_vtiles = tv;
     return RD_OK;
@@ -239,6 +244,9 @@ FitArgs fit_args(rd_ctx* h, const rd_params& p, int nframes, rd_ring* rings, uin
     a.w = p.annulus_halfwidth;
     a.min_pts = p.min_fit_points;
     a.rings = rings;
+    a.stats_in = h->d_stats;
+    a.stats_out = reinterpret_cast<unsigned long long*>(h->dh_stats);
+    a.nstats = NSTATS;
     return a;
 }
 
@@ -270,8 +278,8 @@ void collect_timing(rd_ctx* h, bool with_stencil) {
 // sequence can be captured in a graph.
 rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg, bool with_stencil, int tt, int tv,
                   rd_ring* rings, uint32_t* counts_out) {
-    RD_HIP(launch_zero(h->d_counts, h->max_frames + 4, h->stream));
-    RD_HIP(launch_zero(reinterpret_cast<uint32_t*>(h->d_stats), 2 * NSTATS, h->stream));
+    RD_HIP(launch_zero2(h->d_counts, h->max_frames + 4, reinterpret_cast<uint32_t*>(h->d_stats), 2 * NSTATS,
+                        h->stream));
     if (with_stencil) {
         RD_TRY(mark(h, 0));
         RD_HIP(launch_stencil(stencil_args(h, p, nframes, tt), dtype, rg, h->tune.stencil_tile, false, h->stream));
@@ -332,8 +340,7 @@ rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, in
     } else {
         RD_TRY(enqueue(h, p, nframes, dtype, rg, true, tt, tv, h->dh_rings, h->dh_counts));
     }
-    RD_HIP(hipMemcpyAsync(h->h_stats, h->d_stats, NSTATS * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
-    RD_HIP(hipStreamSynchronize(h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));   // rings, counts and statistics arrive through mappings
     collect_timing(h, true);
     h->mark_now = false;
     return RD_OK;
@@ -407,6 +414,7 @@ rd_status ridge_setup(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n,
     fd.nby = (H + BIN - 1) / BIN;
     h->h_frames[0] = fd;
     RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
+    h->frames_dev_n = 0;                          // not a descriptor set setup_frames knows
     return RD_OK;
 }
 
@@ -529,7 +537,9 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t),
                              hipHostMallocMapped) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_frames), h->max_frames * sizeof(FrameDesc)) == hipSuccess;
-    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_stats), NSTATS * sizeof(uint64_t)) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_stats), NSTATS * sizeof(uint64_t), hipHostMallocMapped) ==
+                   hipSuccess;
+    ok = ok && hipHostGetDevicePointer(reinterpret_cast<void**>(&h->dh_stats), h->h_stats, 0) == hipSuccess;
     ok = ok && hipHostGetDevicePointer(reinterpret_cast<void**>(&h->dh_rings), h->h_rings, 0) == hipSuccess;
     ok = ok && hipHostGetDevicePointer(reinterpret_cast<void**>(&h->dh_counts), h->h_counts, 0) == hipSuccess;
     if (!ok) {
@@ -754,7 +764,6 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
         h->mark_now = false;
         return st;
     }
-    RD_HIP(hipMemcpyAsync(h->h_stats, h->d_stats, NSTATS * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     collect_timing(h, false);
     h->mark_now = false;

@@ -84,6 +84,8 @@ __global__ __launch_bounds__(FNT) void k_fit(FitArgs a) {
         for (int f = 0; f < a.nframes; ++f) a.counts_out[f] = a.peak_count[f];
         a.counts_out[a.nframes] = a.error ? *a.error : 0u;
     }
+    if (blockIdx.x == 0 && a.stats_out)                      // the earlier kernels have finished
+        for (int i = tid; i < a.nstats; i += FNT) a.stats_out[i] = a.stats_in[i];
     for (int f = 0; f < a.nframes; ++f) {
         const FrameDesc fd = a.frames[f];
         const uint32_t np = min(a.peak_count[f], static_cast<uint32_t>(a.max_peaks));

@@ -83,7 +83,12 @@ struct rd_ctx {
     uint32_t* h_counts = nullptr;
     uint32_t* dh_counts = nullptr;
     rd::FrameDesc* h_frames = nullptr;
-    uint64_t* h_stats = nullptr;
+    uint64_t* h_stats = nullptr;        // written by the fit kernel through dh_stats
+    uint64_t* dh_stats = nullptr;
+    // the descriptors d_frames holds (frames_dev_n of them, 0: unknown): an unchanged set is
+    // not uploaded again
+    std::vector<rd::FrameDesc> frames_dev;
+    int frames_dev_n = 0;
     // kernel timing
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

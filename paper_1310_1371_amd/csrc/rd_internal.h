@@ -93,7 +93,10 @@ struct FitArgs {
     int32_t max_peaks;
     int32_t w;
     int32_t min_pts;
-    rd_ring* rings;              // [nframes * max_peaks], slot = frame peak0 + index
+    rd_ring* rings;              // [nframes * max_peaks], slot = frame peak0 + rank
+    const unsigned long long* stats_in;   // statistics counters, copied by block 0 (may be null)
+    unsigned long long* stats_out;        // (host mapped)
+    int32_t nstats;
 };
 
 struct BinArgs {
@@ -122,6 +125,7 @@ size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
 hipError_t vote_prepare();   // one-time kernel attributes (outside any graph capture)
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s);
 hipError_t launch_zero(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_zero2(uint32_t* p, int n, uint32_t* p2, int n2, hipStream_t s);   // both ranges, one launch
 hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s);
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* rk, const uint32_t* bin_count,

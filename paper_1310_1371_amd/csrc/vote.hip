@@ -707,17 +707,22 @@ hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hip
     return hipGetLastError();
 }
 
-__global__ void k_zero(uint32_t* p, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+__global__ void k_zero(uint32_t* p, int n, uint32_t* p2, int n2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n + n2; i += gridDim.x * blockDim.x) {
+        if (i < n) p[i] = 0u;
+        else p2[i - n] = 0u;
+    }
 }
 
 // Zeroing by a kernel rather than a memset node keeps captured graphs replay-safe.
-hipError_t launch_zero(uint32_t* p, int n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
+hipError_t launch_zero2(uint32_t* p, int n, uint32_t* p2, int n2, hipStream_t s) {
+    if (n < 0 || n2 < 0 || n + n2 <= 0) return hipSuccess;
+    const int blocks = (n + n2 + 255) / 256 < 64 ? (n + n2 + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n, p2, n2);
     return hipGetLastError();
 }
+
+hipError_t launch_zero(uint32_t* p, int n, hipStream_t s) { return launch_zero2(p, n, nullptr, 0, s); }
 
 hipError_t launch_bin(const BinArgs& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
