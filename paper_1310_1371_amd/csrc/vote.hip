@@ -74,6 +74,13 @@ constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the
 constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
 constexpr int WC = K_MAX + 8;              // centre tap of the padded weight row
 constexpr int NWW = WC + 4;                // u16 pairs per weight row: taps 0 .. 2 WC + 7
+constexpr int NS_HASH = 64;                // longer strong lists are tested through a hash table
+constexpr int HT = 2048;                   // its slots (u32), in the hotspot list's storage
+static_assert(HT * 4 <= HCAP * 12, "the table lives in the hotspot list's storage");
+static_assert(SCAP <= 0xffff && (NLEV_MAX - 1) < 32, "table entries pack a 16-bit voxel key and a 16-bit index");
+
+// slot of a voxel key (level << 11 | index in the score region) in the strong-voxel table
+__device__ __forceinline__ uint32_t strong_slot(uint32_t key) { return (key * 2654435761u) >> (32 - 11); }
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
 
@@ -558,9 +565,68 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     a.peaks[fd.peak0 + idx] = pk;
                 }
             };
-            // G lanes per strong voxel, each comparing a slice of the list (a long list is the
-            // mark of a ring-centre tile, the slowest work of a launch)
-            const int gs = ns > 256 ? 1 : ns > 128 ? 2 : ns > 32 ? 3 : 0;
+            // a neighbour beats v if its S_int / r is larger, or equal and it comes before v in
+            // (r, y, x) order; a neighbour below the threshold cannot, so only strong ones count
+            auto beats = [&](unsigned long long sv, int lm, int k, int dl, int dy, int dx) {
+                const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
+                const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(lm);
+                const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+                return earlier ? !(lhs > rhs) : !(lhs >= rhs);
+            };
+            if (ns > NS_HASH) {
+                // a long list (the mark of a ring-centre tile, the slowest work of a launch):
+                // the strong voxels go into an open-addressing table keyed by voxel, and each
+                // candidate looks up its 26 neighbours, one task per candidate and level offset.
+                // The hotspot list is not read again in this chunk, so its storage holds the table.
+                uint32_t* const sTab = reinterpret_cast<uint32_t*>(sScratch);
+                for (int i = tid; i < HT; i += NT) sTab[i] = 0xffffffffu;
+                __syncthreads();
+                for (int j = tid; j < ns; j += NT) {
+                    const uint32_t e = sStrongId[j];
+                    const uint32_t key = ((e >> 16) << 11) | (e & 0xffffu);     // distinct per voxel
+                    // at most SCAP of HT slots are taken, so the probe ends
+                    for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1))
+                        if (atomicCAS(&sTab[slot], 0xffffffffu, (key << 16) | static_cast<uint32_t>(j)) == 0xffffffffu)
+                            break;
+                }
+                __syncthreads();
+                for (int task = tid; task < 3 * ns; task += NT) {
+                    const int j = task / 3, dl = task - 3 * j - 1;
+                    int li, lm, sxr, syr;
+                    if (!candidate(j, li, lm, sxr, syr)) continue;
+                    const int nl = li + dl;
+                    if (nl < 0 || nl >= nlev) continue;
+                    const unsigned long long sv = sStrongS[j];
+                    bool peak = true;
+#pragma unroll
+                    for (int o = 0; o < 9; ++o) {
+                        const int dy = o / 3 - 1, dx = o % 3 - 1;
+                        if (dl == 0 && dy == 0 && dx == 0) continue;
+                        // 1 <= sxr, syr <= T: the neighbour lies in the score region's index range
+                        const uint32_t key = (static_cast<uint32_t>(nl) << 11) |
+                                             static_cast<uint32_t>((syr + dy) * SR + sxr + dx);
+                        for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1)) {
+                            const uint32_t v = sTab[slot];
+                            if (v == 0xffffffffu) break;                      // not strong
+                            if ((v >> 16) == key) {
+                                if (beats(sv, lm, static_cast<int>(v & 0xffffu), dl, dy, dx)) peak = false;
+                                break;
+                            }
+                        }
+                    }
+                    if (!peak) sBad[j] = 1;
+                }
+                __syncthreads();
+                for (int j = tid; j < ns; j += NT) {
+                    int li, lm, sxr, syr;
+                    if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
+                }
+                if (c + 1 < a.nchunks) prepare(c + 1);
+                __syncthreads();
+                continue;
+            }
+            // a short list: G lanes per strong voxel, each comparing a slice of the list
+            const int gs = ns > 32 ? 3 : 0;
             const int G = 1 << gs;
             for (int task = tid; task < (ns << gs); task += NT) {
                 const int j = task >> gs, g = task & (G - 1);
@@ -577,11 +643,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int su_idx = static_cast<int>(eu & 0xffffu);
                     const int dy = su_idx / SR - syr, dx = su_idx % SR - sxr;
                     if (dl < -1 || dl > 1 || dy < -1 || dy > 1 || dx < -1 || dx > 1) continue;
-                    const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
-                    const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(lm);
-                    // neighbours before v in (r, y, x) order must be strictly below it
-                    const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                    if (earlier ? !(lhs > rhs) : !(lhs >= rhs)) peak = false;
+                    if (beats(sv, lm, k, dl, dy, dx)) peak = false;
                 }
                 if (G == 1) {
                     if (peak) emit(j, lm, sxr, syr);

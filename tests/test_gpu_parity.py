@@ -52,12 +52,25 @@ def _big_ring():
     return synth.Frame(f.image, f.cx, f.cy, f.R, f.s, f.A, dict(f.params, r_min=100, r_max=126), 0)
 
 
+def _concentric():
+    """300 x 300 float32 with 15 concentric rings (radii 10, 14, ..., 66 px, one centre) and
+    radius bins 8-70: one tile's level chunks hold up to 208 above-threshold voxels, past the
+    64 at which the 3x3x3 test looks neighbours up in a hash table."""
+    R = 10.0 + 4.0 * np.arange(15)
+    k = len(R)
+    cx, cy = np.full(k, 150.3), np.full(k, 149.6)
+    s, A = np.full(k, 1.5), np.ones(k)
+    img = synth.render(300, 300, np.zeros((300, 300)), cx, cy, R, s, A)
+    return synth.Frame(img.astype(np.float32), cx, cy, R, s, A, dict(synth.PARAMS_C1, r_max=70), 0)
+
+
 CASES = {
     "c1_256_f32": lambda: synth.config1(),
     "ragged_300x170_u16": _ragged,
     "min_32x32_f32": lambda: synth.single_ring(32, 32, 15.0, 16.0, 9.3),
     "tail_161x97_f32": _tail,
     "big_ring_300_f32": _big_ring,
+    "concentric_300_f32": _concentric,
 }
 
 
@@ -155,7 +168,7 @@ def _oracle_ridge_inputs(f):
 
 
 @pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32",
-                                  "big_ring_300_f32"])
+                                  "big_ring_300_f32", "concentric_300_f32"])
 def test_accumulator_and_scores_bit_exact(det, name):
     say(f"[accumulate] {name}")
     f = _frame(name)
@@ -223,7 +236,7 @@ def _match(ref, got):
 
 
 @pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32",
-                                  "big_ring_300_f32"])
+                                  "big_ring_300_f32", "concentric_300_f32"])
 def test_rings_from_oracle_ridges_exact(det, name):
     say(f"[rings from oracle ridges] {name}")
     f = _frame(name)
