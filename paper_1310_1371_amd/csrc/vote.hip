@@ -396,6 +396,16 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     // byte offsets of the u16 counters: 2 u within a row, row stride 2 AWP
                     const int x2 = 2 * x, AW2 = 2 * AW, AWP2 = 2 * AWP;
                     int base = 2 * (la - l0) * plane;
+                    // the vote that lifts a counter past T_int lists the voxel as a hotspot, once,
+                    // if it lies in the score region (the tile grown by 1 px).  The slot is taken
+                    // at one level step and written at the next, so the wait for the slot comes
+                    // with the wait for the next vote instead of adding to the step.
+                    uint32_t pend_h = 0xffffffffu, pend_e = 0;
+                    // a per-lane address (always sNh): one atomic per listing lane, whose return
+                    // is read at the next step (a wave-wide combined atomic is read at once)
+                    int zoff = 0;
+                    asm volatile("" : "+v"(zoff));
+                    uint32_t* const nh_ptr = &sNh + zoff;
                     for (int l = la; l <= lb; ++l) {
                         const int u2 = x2 + 2 * (accx >> 14);
                         const int v = y + (accy >> 14);
@@ -405,22 +415,26 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             const int sh = (b & 2) << 3;
                             const uint32_t old = (atomicAdd(&sA[b >> 2], 1u << sh) >> sh) & 0xffffu;
                             ++st_votes;
-                            // the vote that lifts a counter past T_int lists the voxel as a hotspot,
-                            // once, if it lies in the score region (the tile grown by 1 px)
+                            if (pend_h < static_cast<uint32_t>(HCAP)) {
+                                sHot[pend_h] = pend_e;
+                                sHS[pend_h] = 0ull;
+                            }
+                            pend_h = 0xffffffffu;
                             const int u = u2 >> 1;
                             if (old == tint && static_cast<unsigned>(u - hu0) < static_cast<unsigned>(hw) &&
                                 static_cast<unsigned>(v - hv0) < static_cast<unsigned>(hh)) {
-                                const uint32_t h = atomicAdd(&sNh, 1u);
-                                if (h < static_cast<uint32_t>(HCAP)) {
-                                    sHot[h] = (static_cast<uint32_t>(l - l0) << 16) |
-                                              static_cast<uint32_t>((v - hv0 + sy0 - (y0 - 1)) * SR + (u - hu0 + sx0 - (x0 - 1)));
-                                    sHS[h] = 0ull;
-                                }
+                                pend_h = atomicAdd(nh_ptr, 1u);
+                                pend_e = (static_cast<uint32_t>(l - l0) << 16) |
+                                         static_cast<uint32_t>((v - hv0 + sy0 - (y0 - 1)) * SR + (u - hu0 + sx0 - (x0 - 1)));
                             }
                         }
                         accx += sqx;
                         accy += sqy;
                         base += 2 * plane;
+                    }
+                    if (pend_h < static_cast<uint32_t>(HCAP)) {
+                        sHot[pend_h] = pend_e;
+                        sHS[pend_h] = 0ull;
                     }
                 }
                 __syncthreads();
