@@ -479,8 +479,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 }
                 const int nh = static_cast<int>(min(sNh, static_cast<uint32_t>(HCAP)));
                 // one task per hotspot, 8-column band of its window (16-byte aligned in the row)
-                // and half of the window's rows: the band's eight horizontal weights stay in
-                // registers while the task walks its rows with one 16-byte load each
+                // and half of the window's row distances: the band's eight horizontal weights
+                // stay in registers while the task walks its rows with one 16-byte load each
                 const int ntk = 2 * nbm;
                 const uint32_t mB = 0xffffffffu / static_cast<uint32_t>(ntk) + 1u;
                 for (int task = tid; task < nh * ntk; task += NT) {
@@ -499,10 +499,16 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int o = ax0 + c0 - vx + WC;               // WC - K - 7 >= 1, o + 7 < 2 WC
                     const uint32_t* wp = (o & 1) ? &sWpO[li][o >> 1] : &sWpE[li][o >> 1];
                     const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
-                    // rows vy - K .. vy (half 0) or vy + 1 .. vy + K (half 1), clipped to the region
-                    const int ylo = half ? vy + 1 : max(vy - K, ay0), yhi = half ? min(vy + K, ay1 - 1) : vy;
+                    // rows vy - d and vy + d share the weight W(d): the task takes d = 0 .. K/2
+                    // (half 0) or K/2 + 1 .. K (half 1), rows clipped to the region, and weights
+                    // the sum of a pair's two bands once.  A counter at radius r holds at most the
+                    // ridge pixels within about 0.75 px of a circle of radius r (under 2400 for
+                    // r <= 127), so two 8-tap bands of weights <= 2^15 stay below 2^31 and the
+                    // 32-bit sum is exact.
+                    const int dlo = half ? (K >> 1) + 1 : 0, dhi = half ? K : (K >> 1);
+                    const int up_max = vy - ay0, dn_max = ay1 - 1 - vy;   // farthest rows in the region
                     const int rstep = AWP >> 3;
-                    const uint4* row = reinterpret_cast<const uint4*>(sA) + ((li * plane + (ylo - ay0) * AWP + c0) >> 3);
+                    const uint4* rowc = reinterpret_cast<const uint4*>(sA) + ((li * plane + (vy - ay0) * AWP + c0) >> 3);
                     const uint16_t* wv = &sWt[lg][0];
                     unsigned long long acc = 0;
                     auto band = [&](const uint4 q) {
@@ -511,23 +517,24 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         rs = dot2_u16(q.z, w2, rs);
                         return dot2_u16(q.w, w3, rs);
                     };
-                    int yy = ylo;
-                    for (; yy + 3 <= yhi; yy += 4) {           // four independent row loads in flight
-                        const uint4 q0 = row[0], q1 = row[rstep], q2 = row[2 * rstep], q3 = row[3 * rstep];
-                        row += 4 * rstep;
-                        const int d0 = yy - vy;
-                        acc += static_cast<unsigned long long>(wv[d0 < 0 ? -d0 : d0]) * band(q0);
-                        acc += static_cast<unsigned long long>(wv[d0 + 1 < 0 ? -d0 - 1 : d0 + 1]) * band(q1);
-                        acc += static_cast<unsigned long long>(wv[d0 + 2 < 0 ? -d0 - 2 : d0 + 2]) * band(q2);
-                        acc += static_cast<unsigned long long>(wv[d0 + 3 < 0 ? -d0 - 3 : d0 + 3]) * band(q3);
+                    // a row outside the region is read at the nearest row inside (the first and
+                    // last rows always are) and its band replaced by zero
+                    auto row_up = [&](int dd) {
+                        const uint32_t b = band(rowc[-min(dd, up_max) * rstep]);
+                        return dd <= up_max ? b : 0u;
+                    };
+                    auto row_dn = [&](int dd) {
+                        const uint32_t b = band(rowc[min(dd, dn_max) * rstep]);
+                        return (dd > 0 && dd <= dn_max) ? b : 0u;
+                    };
+                    int d = dlo;
+                    for (; d + 1 <= dhi; d += 2) {             // two pairs, four row loads in flight
+                        const uint32_t s0 = row_up(d) + row_dn(d), s1 = row_up(d + 1) + row_dn(d + 1);
+                        acc += static_cast<unsigned long long>(wv[d]) * s0;
+                        acc += static_cast<unsigned long long>(wv[d + 1]) * s1;
                     }
-                    for (; yy <= yhi; ++yy) {
-                        const uint4 q = *row;
-                        row += rstep;
-                        const int dy = yy - vy;
-                        acc += static_cast<unsigned long long>(wv[dy < 0 ? -dy : dy]) * band(q);
-                    }
-                    st_taps += 8 * max(yhi - ylo + 1, 0);
+                    if (d <= dhi) acc += static_cast<unsigned long long>(wv[d]) * (row_up(d) + row_dn(d));
+                    st_taps += 8 * (max(min(dhi, up_max) - dlo + 1, 0) + max(min(dhi, dn_max) - max(dlo, 1) + 1, 0));
                     if (acc) atomicAdd(&sHS[h], acc);
                 }
                 __syncthreads();
