@@ -501,9 +501,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
                     // rows vy - d and vy + d share the weight W(d): the task takes d = 0 .. K/2
                     // (half 0) or K/2 + 1 .. K (half 1), rows clipped to the region, and weights
-                    // the sum of a pair's two bands once.  A counter at radius r holds at most the
-                    // ridge pixels within about 0.75 px of a circle of radius r (under 2400 for
-                    // r <= 127), so two 8-tap bands of weights <= 2^15 stay below 2^31 and the
+                    // the sum of a pair's two bands once.  A counter takes at most one vote per
+                    // lattice offset the rounded r X_- can reach (1016 at r = 127, the largest
+                    // level), so two 8-tap bands of weights <= 2^15 stay below 2^31 and the
                     // 32-bit sum is exact.
                     const int dlo = half ? (K >> 1) + 1 : 0, dhi = half ? K : (K >> 1);
                     const int up_max = vy - ay0, dn_max = ay1 - 1 - vy;   // farthest rows in the region

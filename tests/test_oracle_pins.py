@@ -160,6 +160,25 @@ def _brute_votes(xs, ys, qx, qy, W, H, r_lo, r_hi):
     return A
 
 
+def test_counter_bound_at_the_largest_radius():
+    """A counter at level r receives at most one vote per lattice offset rho(r, q) (a pixel
+    votes once per sign, and its two signs cannot meet at r >= 1), so the number of distinct
+    offsets over every direction code bounds every count.  At r = 127 (r_max <= 126, plus the
+    neighbour level) it stays far below 4096: two 8-tap bands of smoothing weights <= 2^15
+    then sum below 2^31, which the fused kernel relies on."""
+    th = np.linspace(0.0, 2.0 * np.pi, 400_000, endpoint=False)
+    qx, qy = O.direction_code(np.cos(th), np.sin(th))
+    codes = np.unique(np.stack([qx, qy], 1), axis=0)
+    offs = set()
+    for sgn in (1, -1):
+        ox = O.vote_offset(127, sgn * codes[:, 0])
+        oy = O.vote_offset(127, sgn * codes[:, 1])
+        offs.update(zip(ox.tolist(), oy.tolist()))
+    n = len(offs)
+    assert 2 * np.pi * 127 < n < 1600
+    assert 16 * n * 2 ** 15 < 2 ** 31
+
+
 def test_vote_matches_brute_force():
     rng = np.random.default_rng(7)
     W, H = 24, 20
