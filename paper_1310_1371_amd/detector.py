@@ -48,9 +48,11 @@ def _frame_struct(frame):
     return N.RdFrame(arr.shape[1], arr.shape[0], arr.strides[0], dt, 0, arr.ctypes.data)
 
 
-def rings_to_numpy(buf, n: int) -> np.ndarray:
-    out = np.frombuffer(buf, dtype=RING_DTYPE, count=n).copy() if n else np.zeros(0, RING_DTYPE)
-    return out
+def _copy_rings(raw: np.ndarray, first: int, n: int) -> np.ndarray:
+    """Rings first .. first + n - 1 of a byte view of a ring buffer, as a new RING_DTYPE array.
+    Copied as bytes: numpy copies a structured array field by field (~8 us for 200 rings)."""
+    sz = RING_DTYPE.itemsize
+    return raw[first * sz:(first + n) * sz].copy().view(RING_DTYPE)
 
 
 class Detector:
@@ -69,7 +71,9 @@ class Detector:
         self.default_tuning = self.get_tuning()
         self.max_peaks = max_peaks
         self._rings = (N.RdRing * max_peaks)()
+        self._rings_raw = np.frombuffer(self._rings, dtype=np.uint8)   # shares self._rings
         self._batch_buf = None
+        self._batch_meta = None          # (frames, capacity, offsets, capacities) of the last batch
 
     def close(self):
         if getattr(self, "_h", None):
@@ -96,7 +100,7 @@ class Detector:
         st = self._lib.rd_detect(self._h, ctypes.byref(fr), ctypes.byref(p), self._rings, self.max_peaks,
                                  ctypes.byref(n))
         N.check(st, "rd_detect")
-        return rings_to_numpy(self._rings, n.value)
+        return _copy_rings(self._rings_raw, 0, n.value)
 
     def detect_from_ridges(self, xy: torch.Tensor, q: torch.Tensor, width: int, height: int,
                            params: dict) -> np.ndarray:
@@ -106,7 +110,7 @@ class Detector:
         st = self._lib.rd_detect_ridges(self._h, xy.data_ptr(), q.data_ptr(), xy.shape[0], width, height,
                                         ctypes.byref(p), self._rings, self.max_peaks, ctypes.byref(n))
         N.check(st, "rd_detect_ridges")
-        return rings_to_numpy(self._rings, n.value)
+        return _copy_rings(self._rings_raw, 0, n.value)
 
     # -------------------------------------------------------------------- batches
     def _frame_array(self, frames):
@@ -127,13 +131,16 @@ class Detector:
             self._batch_buf = np.empty(n * cap, dtype=RING_DTYPE)
         buf = self._batch_buf
         out = ctypes.cast(buf.ctypes.data, ctypes.POINTER(N.RdRing))
-        offs = (ctypes.c_int64 * n)(*[i * cap for i in range(n)])
-        caps = (ctypes.c_int32 * n)(*([cap] * n))
+        if self._batch_meta is None or self._batch_meta[:2] != (n, cap):
+            self._batch_meta = (n, cap, (ctypes.c_int64 * n)(*[i * cap for i in range(n)]),
+                                (ctypes.c_int32 * n)(*([cap] * n)))
+        offs, caps = self._batch_meta[2], self._batch_meta[3]
         counts = (ctypes.c_int32 * n)()
         p = N.make_params(params)
         st = self._lib.rd_detect_batch(self._h, arr, n, ctypes.byref(p), out, offs, caps, counts)
         N.check(st, "rd_detect_batch")
-        return [buf[i * cap:i * cap + counts[i]].copy() for i in range(n)]
+        raw = buf.view(np.uint8)
+        return [_copy_rings(raw, i * cap, counts[i]) for i in range(n)]
 
     def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = None, use_graph: bool = True):
         """Launch choices (no result depends on them); vote_lds_kb None keeps the largest."""
