@@ -339,6 +339,27 @@ def test_detect_host_frame_and_repeat_is_bitwise(det):
     assert a.tobytes() == b.tobytes() == c.tobytes()
 
 
+def test_same_storage_different_views(det):
+    """Calls alternating between two views that share one base pointer (a full frame and its
+    top-left corner, the pitch kept): the context keeps the frame descriptors of the last
+    call on the device and uploads new ones only when they differ, so each call must still
+    see its own view.  Each result is compared with a fresh context's."""
+    from paper_1310_1371_amd.detector import Detector
+    say("[detect] alternating views of one buffer")
+    f = synth.config2(seed=31, W=512, H=384, n_rings=40)
+    full = torch.from_numpy(f.image).cuda()
+    part = full[:256, :320]
+    with_fresh = []
+    for view in (full, part):
+        d2 = Detector(max_width=2048, max_height=2048, max_peaks=65536)
+        with_fresh.append(d2.detect(view, f.params))
+        d2.close()
+    assert len(with_fresh[0]) > len(with_fresh[1]) > 0
+    for _ in range(2):
+        for view, ref in ((full, with_fresh[0]), (part, with_fresh[1]), (full, with_fresh[0])):
+            assert det.detect(view, f.params).tobytes() == ref.tobytes()
+
+
 def test_constant_frame_has_no_rings(det):
     say("[detect] constant frame")
     img = np.full((64, 96), 7.0, np.float32)
