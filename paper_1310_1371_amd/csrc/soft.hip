@@ -196,56 +196,58 @@ __global__ __launch_bounds__(NT) void k_soft_fwd(SoftFwdArgs a) {
             bins[k] = bin;
         }
     }
-    uint32_t nb = 0, npairs = 0;
+    uint32_t nb = 0, nrid = 0;
     const uint32_t pos = block_scan(keep[0] + keep[1], sWave, &nb);
-    const uint32_t pre = block_scan(2u * (cnt[0] + cnt[1]), sWave, &npairs);
+    const uint32_t pre = block_scan(cnt[0] + cnt[1], sWave, &nrid);
     if (keep[0]) {
         sBin[pos] = bins[0];
         sPre[pos] = pre;
     }
     if (keep[1]) {
         sBin[pos + keep[0]] = bins[1];
-        sPre[pos + keep[0]] = pre + 2u * cnt[0];
+        sPre[pos + keep[0]] = pre + cnt[0];
     }
-    if (tid == 0) sPre[nb] = npairs;
+    if (tid == 0) sPre[nb] = nrid;
     __syncthreads();
 
-    // ---- splat every (ridge, sign) pair over the levels whose footprint meets the tile
-    for (uint32_t pi = tid; pi < npairs; pi += NT) {
-        uint32_t lo = 0, hi = nb;          // largest k with sPre[k] <= pi
+    // ---- splat every ridge, both signs, over the levels whose footprint meets the tile (one
+    // lane per ridge: the bin search and the loads are shared by the two signs)
+    for (uint32_t ri = tid; ri < nrid; ri += NT) {
+        uint32_t lo = 0, hi = nb;          // largest k with sPre[k] <= ri
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (sPre[mid] <= pi) lo = mid;
+            if (sPre[mid] <= ri) lo = mid;
             else hi = mid;
         }
-        const uint32_t local = pi - sPre[lo];
-        const int64_t slot = static_cast<int64_t>(sBin[lo]) * BIN_CAP + (local >> 1);
-        const double sgn = (local & 1u) ? -1.0 : 1.0;
+        const int64_t slot = static_cast<int64_t>(sBin[lo]) * BIN_CAP + (ri - sPre[lo]);
         const uint32_t v = a.sxy[slot];
         const int x = static_cast<int>(v & 0xffffu), y = static_cast<int>(v >> 16);
         const double ux = a.sux[slot], uy = a.suy[slot];
         const double w = static_cast<double>(a.sw[slot]);
-        int r0 = ra, r1 = rb;
-        clip_axis(x, sgn * ux, tx0 - 1.0, tx0 + static_cast<double>(ST), r0, r1);
-        clip_axis(y, sgn * uy, ty0 - 1.0, ty0 + static_cast<double>(ST), r0, r1);
-        for (int r = r0; r <= r1; ++r) {
-            const double sr = sgn * r;
-            const double px = splat_pos(x, sr, ux), py = splat_pos(y, sr, uy);
-            const double fi = floor(px), fj = floor(py);
-            const double fx = px - fi, fy = py - fj;
-            const int ci = static_cast<int>(fi) - tx0, cj = static_cast<int>(fj) - ty0;
-            float* lvl = sAcc + (r - ra) * ST * ST;
+        for (int sg = 0; sg < 2; ++sg) {
+            const double sgn = sg ? -1.0 : 1.0;
+            int r0 = ra, r1 = rb;
+            clip_axis(x, sgn * ux, tx0 - 1.0, tx0 + static_cast<double>(ST), r0, r1);
+            clip_axis(y, sgn * uy, ty0 - 1.0, ty0 + static_cast<double>(ST), r0, r1);
+            for (int r = r0; r <= r1; ++r) {
+                const double sr = sgn * r;
+                const double px = splat_pos(x, sr, ux), py = splat_pos(y, sr, uy);
+                const double fi = floor(px), fj = floor(py);
+                const double fx = px - fi, fy = py - fj;
+                const int ci = static_cast<int>(fi) - tx0, cj = static_cast<int>(fj) - ty0;
+                float* lvl = sAcc + (r - ra) * ST * ST;
 #pragma unroll
-            for (int dj = 0; dj < 2; ++dj) {
-                const int yy = cj + dj;
-                if (yy < 0 || yy >= ST || ty0 + yy >= a.H) continue;
-                const double by = dj ? fy : 1.0 - fy;
+                for (int dj = 0; dj < 2; ++dj) {
+                    const int yy = cj + dj;
+                    if (yy < 0 || yy >= ST || ty0 + yy >= a.H) continue;
+                    const double by = dj ? fy : 1.0 - fy;
 #pragma unroll
-                for (int di = 0; di < 2; ++di) {
-                    const int xx = ci + di;
-                    if (xx < 0 || xx >= ST || tx0 + xx >= a.W) continue;
-                    const double bx = di ? fx : 1.0 - fx;
-                    atomicAdd(&lvl[yy * ST + xx], static_cast<float>(w * (bx * by)));
+                    for (int di = 0; di < 2; ++di) {
+                        const int xx = ci + di;
+                        if (xx < 0 || xx >= ST || tx0 + xx >= a.W) continue;
+                        const double bx = di ? fx : 1.0 - fx;
+                        atomicAdd(&lvl[yy * ST + xx], static_cast<float>(w * (bx * by)));
+                    }
                 }
             }
         }
