@@ -12,7 +12,7 @@
 //   k_soft_fwd      one workgroup per (32x32 tile, 8 levels): gathers the bins whose ridges
 //                   can reach the tile at those radii, clips each (ridge, sign) ray to the
 //                   tile, splats into LDS with float atomics, writes the tile once
-//   k_soft_bwd      one wave per ridge: lanes over (level, sign), gathers the upstream
+//   k_soft_bwd      one wave per ridge: lanes over levels, both signs, gathers the upstream
 //                   gradient at the 4 splat cells, reduces d/dw and d/dX_-, then applies the
 //                   eigen adjoint -> d/d(Ixx, Iyy, Ixy)
 //   k_scatter       per-ridge Hessian gradients -> three planes
@@ -279,9 +279,11 @@ __global__ __launch_bounds__(NT) void k_soft_bwd(SoftBwdArgs a) {
         const Geo g = geometry(a.hess[3 * i], a.hess[3 * i + 1], a.hess[3 * i + 2]);
         const double w = -g.km;
         double gw = 0.0, gux = 0.0, guy = 0.0;
-        for (int pidx = lane; pidx < 2 * a.L; pidx += 64) {
-            const int li = pidx >> 1;
-            const double sgn = (pidx & 1) ? -1.0 : 1.0;
+        // one lane per level, both signs (2L pairs in one round of 64 lanes up to L = 64)
+        for (int li = lane; li < a.L; li += 64)
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const double sgn = sg ? -1.0 : 1.0;
             const double sr = sgn * (a.r_lo + li);
             const double px = splat_pos(x, sr, g.ux), py = splat_pos(y, sr, g.uy);
             const double fi = floor(px), fj = floor(py);
