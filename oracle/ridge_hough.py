@@ -29,7 +29,8 @@ TWO_PI = 6.283185307179586
 
 DEFAULTS = dict(sigma_smooth=2.0, k_threshold=-0.02, r_min=8, r_max=40, vote_threshold=3,
                 peak_fraction=0.4, sig_slope=0.05, sig_icpt=0.25, annulus_halfwidth=2,
-                min_fit_points=8)
+                min_fit_points=8, measure=0)
+MEASURE_RIDGE, MEASURE_EDGE = 0, 1     # directed ridges (Hessian) or directed edges (gradient)
 
 
 def f32(v) -> float:
@@ -154,6 +155,37 @@ def nms_offsets(qx, qy):
     return nx, ny
 
 
+# --------------------------------------------------------------------------------------
+# Directed edges (SI, "Additional notes": the Hessian may be replaced by the gradient; its
+# magnitude then takes the place of k_- and must be a local maximum along the gradient)
+# --------------------------------------------------------------------------------------
+
+def gradient(img: np.ndarray, sigma: float):
+    """Ix, Iy of the smoothed image from 5x5 first-order Sobel kernels (D1 along the
+    derivative, S5 across) divided by 128, so the result is in image units per px
+    (READING)."""
+    G = gaussian_smooth(img, sigma)
+    Ix = correlate_y(correlate_x(G, SOBEL_D1), SOBEL_S5) / 128.0
+    Iy = correlate_y(correlate_x(G, SOBEL_S5), SOBEL_D1) / 128.0
+    return Ix, Iy
+
+
+def edge_measure(img, sigma):
+    """m = -|grad I| (float64) and the direction code of the unit gradient for every
+    pixel.  READING: the measure is negated so that the ridge criterion below (m under the
+    threshold and a strict minimum along the direction) reads "|grad I| above -T and a
+    strict maximum along the gradient"; where the gradient vanishes the direction is
+    (0, 1), as at an isotropic Hessian."""
+    Ix, Iy = gradient(img, sigma)
+    g = np.sqrt(Ix * Ix + Iy * Iy)
+    nz = g > 0.0
+    safe = np.where(nz, g, 1.0)
+    ux = np.where(nz, Ix / safe, 0.0)
+    uy = np.where(nz, Iy / safe, 1.0)
+    qx, qy = direction_code(ux, uy)
+    return -g, qx, qy
+
+
 def ridge_mask(km, qx, qy, k_threshold):
     """Ridge if k_- < T_k and k_- strictly below both neighbours along X_-.  READING:
     pixels on the 1-px frame border are never ridges."""
@@ -171,9 +203,13 @@ def ridge_mask(km, qx, qy, k_threshold):
 
 
 def ridges(img, params):
-    """Ridge list in raster order: (x, y, qx, qy, k) arrays."""
+    """Ridge list in raster order: (x, y, qx, qy, k) arrays; with measure = 1 the directed
+    edges, k then holding -|grad I|."""
     p = dict(DEFAULTS, **params)
-    km, qx, qy = curvature(np.asarray(img, dtype=np.float64), f32(p["sigma_smooth"]))
+    if int(p["measure"]) == MEASURE_EDGE:
+        km, qx, qy = edge_measure(np.asarray(img, dtype=np.float64), f32(p["sigma_smooth"]))
+    else:
+        km, qx, qy = curvature(np.asarray(img, dtype=np.float64), f32(p["sigma_smooth"]))
     m = ridge_mask(km, qx, qy, f32(p["k_threshold"]))
     ys, xs = np.nonzero(m)
     return xs.astype(np.int64), ys.astype(np.int64), qx[ys, xs], qy[ys, xs], km[ys, xs]

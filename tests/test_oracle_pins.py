@@ -77,6 +77,70 @@ def test_hessian_equals_full_2d_kernel_with_mirror_border():
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10)
 
 
+# ---------------------------------------------------------------- directed-edge gradient
+
+def test_gradient_exact_on_linear_ramps():
+    """On I = a x + b y + c the normalised Gaussian keeps the ramp and the first-order Sobel
+    pair divided by 128 returns (a, b) exactly, away from the mirrored border."""
+    y, x = np.mgrid[0:64, 0:72].astype(np.float64)
+    for a, b in ((0.7, -0.3), (-2.5, 0.0), (0.0, 1.25)):
+        Ix, Iy = O.gradient(a * x + b * y + 5.0, 2.0)
+        np.testing.assert_allclose(Ix[12:-12, 12:-12], a, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(Iy[12:-12, 12:-12], b, rtol=0, atol=1e-12)
+
+
+def test_gradient_equals_full_2d_kernel_with_mirror_border():
+    """The separable gradient equals one 2D correlation of the raw image with the composite
+    (Gaussian * Sobel) kernel under scipy's 'mirror' border (= reflect-101)."""
+    rng = np.random.default_rng(7)
+    img = rng.normal(0, 1, (37, 41)) * 100 + 500
+    Ix, Iy = O.gradient(img, 2.0)
+    S5 = [1, 4, 6, 4, 1]
+    D1 = [-1, -2, 0, 2, 1]
+    for got, ky, kx in ((Ix, S5, D1), (Iy, D1, S5)):
+        ref = ndi.correlate(img, _full_kernel(ky, kx, 2.0) / 128.0, mode="mirror")
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10)
+
+
+def _disc(W, H, cx, cy, R):
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    return (np.hypot(x - cx, y - cy) < R).astype(np.float64)
+
+
+def test_edge_measure_of_a_disc():
+    """A uniform disc: -|grad I| is strongest on the rim (the measure's minimum along the
+    row through the centre lies within one pixel of x = c +/- R), and each edge pixel's code
+    is the radial direction (the unit gradient points at the centre, up to the sign the code
+    canonicalises)."""
+    c, R = 60, 23.3
+    img = _disc(121, 121, c, c, R)
+    m, qx, qy = O.edge_measure(img, 2.0)
+    row = m[c]
+    assert abs(int(np.argmin(row[:c])) - (c - R)) <= 1.0
+    assert abs(int(c + np.argmin(row[c:])) - (c + R)) <= 1.0
+    xs, ys, eqx, eqy, k = O.ridges(img, dict(O.DEFAULTS, measure=O.MEASURE_EDGE, k_threshold=-0.02))
+    assert len(xs) > 100
+    d = np.hypot(xs - c, ys - c)
+    assert np.all(np.abs(d - R) < 1.5)
+    cos = np.abs(eqx * (xs - c) + eqy * (ys - c)) / (O.Q_ONE * d)
+    assert cos.min() > 0.99
+
+
+def test_edge_mode_finds_a_disc_at_its_centre_and_radius():
+    """With directed edges a uniform disc of radius R gives its strongest ring at the disc's
+    centre, and the Kasa fit of its rim lands within 0.05 px of the centre and 0.3 px of R
+    (a blurred disc's steepest point moves outward by about sigma^2 / 2R)."""
+    c, R = 60, 23.3
+    img = _disc(121, 121, c, c, R)
+    p = dict(O.DEFAULTS, measure=O.MEASURE_EDGE, k_threshold=-0.02, r_min=8, r_max=40)
+    rings = O.detect(img, p)
+    top = rings[np.argmax(rings["score"])]
+    assert (top["a"], top["b"]) == (c, c)
+    assert top["fit_ok"] == 1
+    assert abs(top["cx"] - c) < 0.05 and abs(top["cy"] - c) < 0.05
+    assert abs(top["r"] - R) < 0.3
+
+
 # ---------------------------------------------------------------- eigensolve
 
 def test_eigen_matches_numpy_eigh():
