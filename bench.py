@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="frames of the batched measurement (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--uneven", type=int, default=64, help="frames of the uneven batch (0: skip)")
+    ap.add_argument("--edge-steps", type=int, default=100, help="plain steps with directed edges (0: skip)")
     ap.add_argument("--diff-frames", type=int, default=16, help="frames of the differentiable step (0: skip)")
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--stream-launches", type=int, default=3, help="32-frame launches of the stream (0: skip)")
@@ -301,6 +302,10 @@ def main():
         del uframes
 
     # ---- differentiable step
+    if args.edge_steps > 0:
+        log(f"[bench] directed edges, {args.edge_steps} plain steps")
+        out["edges"] = edges(det, frame, p, W, H, args, torch)
+
     if args.diff_frames > 0:
         log(f"[bench] differentiable step on {args.diff_frames} frames")
         out["differentiable"] = differentiable(det, args, np, torch, synth)
@@ -315,6 +320,34 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
     print(json.dumps(out), flush=True)
     det.close()
+
+
+def edges(det, frame, p, W, H, args, torch):
+    """The plain path with directed edges (gradient magnitude as the measure) on the same
+    frame: T = -12 counts / px, a quarter of the weakest ring's smoothed gradient."""
+    pe = dict(p, measure=1, k_threshold=-12.0)
+    for _ in range(5):
+        rings = det.detect(frame, pe)
+    n_edge = det.stats()["ridges"]
+    det.enable_timing(True)
+    det.read_timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.edge_steps):
+        rings = det.detect(frame, pe)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timing = det.read_timing(reset=True)
+    det.enable_timing(False)
+    kms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in timing.items()}
+    L = p["r_max"] - p["r_min"] + 3
+    lds_bytes = 4 * W * H * L + 4 * 2 * L * n_edge          # the byte count of the roofline above
+    return {"value": W * H * args.edge_steps / dt / 1e6, "unit": "Mpixel/s", "frames_per_s": args.edge_steps / dt,
+            "ms_per_step": dt / args.edge_steps * 1e3, "kernel_ms": kms, "edge_pixels": int(n_edge),
+            "rings_found": int(len(rings)),
+            "vote_roofline_frac": lds_bytes / (kms["vote"] * 1e-3) / 1e9 / LDS_PEAK_GBS,
+            "workload": "plain rd_detect with directed edges (measure 1, T = -12 counts/px) on the same "
+                        "1024x1024 u16 frame"}
 
 
 def differentiable(det, args, np, torch, synth):

@@ -63,11 +63,22 @@ typedef struct {
     const void* data;
 } rd_frame;
 
+/* Feature measure of steps 1-2 (rd_params.measure).  RD_MEASURE_RIDGE: directed ridges, the
+ * smaller Hessian eigenvalue k_- and its eigenvector X_- (Results, "Directed ridge detection &
+ * votes collection").  RD_MEASURE_EDGE: directed edges (SI, "Additional notes": the gradient
+ * replaces the Hessian and its magnitude must be a local maximum along the gradient); the
+ * measure is m = -|grad I| (first-order 5x5 Sobel / 128 on the smoothed frame) and the
+ * direction the unit gradient, so that k_threshold and the strict-minimum test read
+ * "|grad I| > -k_threshold and a strict maximum along the gradient".  Steps 3-5 are the same
+ * for both. */
+enum { RD_MEASURE_RIDGE = 0, RD_MEASURE_EDGE = 1 };
+
 /* The method's knobs.  Limits checked by rd_validate_params are given per field. */
 typedef struct {
     float sigma_smooth;       /* Gaussian scale-selection sigma, px; 0 < s <= 4 (Results,
                                  scale selection at about the outer ring's scale)          */
-    float k_threshold;        /* curvature threshold T_k <= 0, image units / px^2 (SI step 2) */
+    float k_threshold;        /* threshold T_k <= 0 on the measure: curvature, image units /
+                                 px^2 (SI step 2); with directed edges -|grad I|, units / px */
     int32_t r_min, r_max;     /* radius range, 1 <= r_min <= r_max <= 126, step 1 px       */
     int32_t vote_threshold;   /* integer hotspot threshold: A > vote_threshold (SI step 4) */
     float peak_fraction;      /* f: a peak needs S > f * 2 pi (SI step 4), 0 <= f          */
@@ -75,6 +86,8 @@ typedef struct {
     float sig_icpt;           /* slope >= 0, icpt > 0, ceil(3 sigma(r_max + 1)) <= 24      */
     int32_t annulus_halfwidth;/* w: members satisfy (r-w)^2 <= d^2 <= (r+w)^2, 0 <= w <= 64 */
     int32_t min_fit_points;   /* fewer annulus members than this: fit_ok = 0, >= 3         */
+    int32_t measure;          /* RD_MEASURE_RIDGE or RD_MEASURE_EDGE; the differentiable
+                                 entry points (rd_soft_*, rd_hessian_backward) take ridges only */
 } rd_params;
 
 /* One detected ring.  (a, b, r_bin) is the Hough peak voxel; (cx, cy, r) the circle fit

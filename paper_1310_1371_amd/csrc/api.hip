@@ -140,6 +140,7 @@ StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_t
     }
     for (int i = 0; i <= RG_MAX; ++i) a.g[i] = i <= R ? g[i] / sum : 0.0;
     a.k_threshold = p.k_threshold;
+    a.edge = p.measure == RD_MEASURE_EDGE ? 1 : 0;
     a.rxy = h->d_rxy;
     a.rq = h->d_rq;
     a.rk = h->d_rk;
@@ -466,6 +467,7 @@ rd_status rd_validate_params(const rd_params* p) {
     if (level_radius(*p, p->r_max + 1) > K_MAX) return RD_E_INVALID;
     if (p->annulus_halfwidth < 0 || p->annulus_halfwidth > 64) return RD_E_INVALID;
     if (p->min_fit_points < 3) return RD_E_INVALID;
+    if (p->measure != RD_MEASURE_RIDGE && p->measure != RD_MEASURE_EDGE) return RD_E_INVALID;
     return RD_OK;
 }
 

@@ -117,6 +117,7 @@ rd_status rd_soft_ridges(rd_handle h, const rd_frame* frame, const rd_params* pa
     if (!h || !params || !n_ridges || capacity < 0) return RD_E_INVALID;
     *n_ridges = 0;
     RD_TRY(rd_validate_params(params));
+    if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
     RD_TRY(check_frame(h, frame));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;
@@ -143,6 +144,7 @@ rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess
                           int32_t height, const rd_params* params, float* acc_dev) {
     if (!h || !params || !acc_dev || n < 0 || (n > 0 && (!xy_dev || !hess_dev))) return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
+    if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;
@@ -190,6 +192,7 @@ rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hes
     if (!h || !params || n < 0 || (n > 0 && (!xy_dev || !hess_dev || !grad_acc_dev || !grad_hess_dev)))
         return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
+    if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;
@@ -218,6 +221,7 @@ rd_status rd_hessian_backward(rd_handle h, const int32_t* xy_dev, const double* 
                               int32_t width, int32_t height, const rd_params* params, float* grad_img_dev) {
     if (!h || !params || !grad_img_dev || n < 0 || (n > 0 && (!xy_dev || !grad_hess_dev))) return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
+    if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;

@@ -42,18 +42,9 @@ __device__ __forceinline__ float load_px(const void* img, int64_t pitch, int x, 
 // Direction code of X_- for the eigenvalue t - d of [[t+h, c], [c, t-h]], d = sqrt(h^2+c^2).
 // The eigenvector is (-c, h + d) for h >= 0 and (h - d, c) for h < 0 (no cancellation in
 // either branch); at an isotropic point (d == 0) X_- = (0, 1).
-__device__ __forceinline__ uint32_t direction_code(double h, double c, double d) {
-    double vx, vy;
-    if (d == 0.0) {
-        vx = 0.0;
-        vy = 1.0;
-    } else if (h >= 0.0) {
-        vx = -c;
-        vy = h + d;
-    } else {
-        vx = h - d;
-        vy = c;
-    }
+// Code of the direction of a nonzero vector (vx, vy): rint(2^14 v / |v|) per component, the
+// sign chosen so that qy > 0, or qy == 0 and qx > 0.
+__device__ __forceinline__ uint32_t vector_code(double vx, double vy) {
     const double inv = 16384.0 / sqrt(vx * vx + vy * vy);
     int qx = static_cast<int>(rint(vx * inv));
     int qy = static_cast<int>(rint(vy * inv));
@@ -62,6 +53,16 @@ __device__ __forceinline__ uint32_t direction_code(double h, double c, double d)
         qy = -qy;
     }
     return (static_cast<uint32_t>(qx) & 0xffffu) | (static_cast<uint32_t>(qy) << 16);
+}
+
+__device__ __forceinline__ uint32_t direction_code(double h, double c, double d) {
+    if (d == 0.0) return vector_code(0.0, 1.0);
+    return h >= 0.0 ? vector_code(-c, h + d) : vector_code(h - d, c);
+}
+
+// Directed edges: the unit gradient's code, (0, 1) where the gradient vanishes.
+__device__ __forceinline__ uint32_t gradient_code(double ix, double iy, double g) {
+    return g == 0.0 ? vector_code(0.0, 1.0) : vector_code(ix, iy);
 }
 
 // Neighbour offset along X_-: nearest of the 8 lattice directions, in integers
@@ -232,7 +233,15 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
 #pragma unroll
             for (int m = 0; m < MS; ++m) {
                 const int r = r0 + m;
-                if (r < KH) {
+                if (r < KH && a.edge) {
+                    // directed edges: Ix = S5_y D1_x G / 128, Iy = D1_y S5_x G / 128, m = -|grad I|
+                    const double ix = ((d1x[m] + d1x[m + 4]) + 4.0 * (d1x[m + 1] + d1x[m + 3]) + 6.0 * d1x[m + 2]) * (1.0 / 128.0);
+                    const double iy = ((s5x[m + 4] - s5x[m]) + 2.0 * (s5x[m + 3] - s5x[m + 1])) * (1.0 / 128.0);
+                    const double g = sqrt(ix * ix + iy * iy);
+                    const double k = -g;
+                    sK[r * KW + c] = k;
+                    sQ[r * KW + c] = (DENSE || k < kthr) ? gradient_code(ix, iy, g) : 0u;
+                } else if (r < KH) {
                     const double ixx = ((d2x[m] + d2x[m + 4]) + 4.0 * (d2x[m + 1] + d2x[m + 3]) + 6.0 * d2x[m + 2]) * (1.0 / 64.0);
                     const double iyy = ((s5x[m] + s5x[m + 4]) - 2.0 * s5x[m + 2]) * (1.0 / 64.0);
                     const double ixy = ((d1x[m + 4] - d1x[m]) + 2.0 * (d1x[m + 3] - d1x[m + 1])) * (1.0 / 64.0);

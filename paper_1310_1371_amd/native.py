@@ -23,7 +23,8 @@ class RdParams(ctypes.Structure):
                 ("r_min", ctypes.c_int32), ("r_max", ctypes.c_int32),
                 ("vote_threshold", ctypes.c_int32), ("peak_fraction", ctypes.c_float),
                 ("sig_slope", ctypes.c_float), ("sig_icpt", ctypes.c_float),
-                ("annulus_halfwidth", ctypes.c_int32), ("min_fit_points", ctypes.c_int32)]
+                ("annulus_halfwidth", ctypes.c_int32), ("min_fit_points", ctypes.c_int32),
+                ("measure", ctypes.c_int32)]
 
 
 class RdRing(ctypes.Structure):
@@ -117,4 +118,5 @@ def check(status: int, what: str, ok=(RD_OK,)):
 def make_params(d: dict) -> RdParams:
     return RdParams(float(d["sigma_smooth"]), float(d["k_threshold"]), int(d["r_min"]), int(d["r_max"]),
                     int(d["vote_threshold"]), float(d["peak_fraction"]), float(d["sig_slope"]),
-                    float(d["sig_icpt"]), int(d["annulus_halfwidth"]), int(d["min_fit_points"]))
+                    float(d["sig_icpt"]), int(d["annulus_halfwidth"]), int(d["min_fit_points"]),
+                    int(d.get("measure", 0)))

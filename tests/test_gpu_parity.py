@@ -290,6 +290,90 @@ def test_end_to_end_rings(det, name):
     assert unmatched <= max(1, 0.01 * len(ref))
 
 
+# ---------------------------------------------------------------- directed edges
+
+def _edge_disc():
+    """121 x 121 float32 uniform disc of radius 23.3 around a pixel centre."""
+    y, x = np.mgrid[0:121, 0:121].astype(np.float64)
+    img = (np.hypot(x - 60, y - 60) < 23.3).astype(np.float32)
+    return synth.Frame(img, np.array([60.0]), np.array([60.0]), np.array([23.3]), np.ones(1), np.ones(1),
+                       dict(synth.PARAMS_C1, measure=O.MEASURE_EDGE), 0)
+
+
+def _edge_c1():
+    """c1 with directed edges: T at a quarter of the weakest ring's smoothed gradient."""
+    f = synth.config1()
+    return synth.Frame(f.image, f.cx, f.cy, f.R, f.s, f.A, dict(f.params, measure=O.MEASURE_EDGE, k_threshold=-0.03), 0)
+
+
+def _edge_ragged():
+    """300 x 170 uint16 c2-like frame with directed edges (T = -12 counts / px)."""
+    f = synth.config2(seed=21, W=300, H=170, n_rings=12)
+    return synth.Frame(f.image, f.cx, f.cy, f.R, f.s, f.A, dict(f.params, measure=O.MEASURE_EDGE, k_threshold=-12.0), 0)
+
+
+EDGE_CASES = {"disc_121_f32": _edge_disc, "c1_256_f32": _edge_c1, "ragged_300x170_u16": _edge_ragged}
+
+
+def _check_edge_measure(det, f):
+    p = f.params
+    m_ref, qx_ref, qy_ref = O.edge_measure(f.image.astype(np.float64), O.f32(p["sigma_smooth"]))
+    m, q = det.curvature(torch.from_numpy(f.image).cuda(), p)
+    m = m.cpu().numpy().astype(np.float64)
+    q = q.cpu().numpy().astype(np.int64)
+    err = np.abs(m - m_ref)
+    assert np.all(err <= _ktol(m_ref)), float((err / _ktol(m_ref)).max())
+    # the direction is undefined where the gradient is within rounding of zero
+    defined = -m_ref > 1e-9 * np.abs(f.image).max()
+    dqx, dqy = np.abs(q[..., 0] - qx_ref), np.abs(q[..., 1] - qy_ref)
+    flips = int((((dqx > 0) | (dqy > 0)) & defined).sum())
+    say(f"  |grad| max rel err {float((err / np.maximum(np.abs(m_ref), 1e-300)).max()):.2e}; q flips {flips}")
+    assert max(dqx[defined].max(), dqy[defined].max()) <= 1
+    assert flips <= max(1, 1e-5 * m.size)
+
+
+@pytest.mark.parametrize("name", list(EDGE_CASES))
+def test_edge_measure_parity(det, name):
+    say(f"[edges: measure] {name}")
+    _check_edge_measure(det, EDGE_CASES[name]())
+
+
+@pytest.mark.parametrize("name", list(EDGE_CASES))
+def test_edge_sets_and_rings(det, name):
+    say(f"[edges: pixels and rings] {name}")
+    f = EDGE_CASES[name]()
+    ref, got, n = _ridge_sets(det, f)
+    sym = set(ref) ^ set(got)
+    say(f"  oracle {len(ref)} edge pixels, gpu {len(got)}, mismatched {len(sym)}")
+    assert len(ref) > 50 and len(sym) <= max(0, int(1e-4 * len(ref)))
+    ring_ref, ring_got, n_common, unmatched = _end_to_end(det, f, torch.from_numpy(f.image).cuda())
+    say(f"  rings: oracle {len(ring_ref)} gpu {len(ring_got)} matched {n_common} unmatched {unmatched}")
+    assert len(ring_ref) > 0 and unmatched <= max(1, 0.01 * len(ring_ref))
+
+
+def test_edge_c2_full(det):
+    """The headline 1024^2 u16 frame with directed edges, as bench.py times it: measure,
+    edge-pixel set and rings against the oracle."""
+    say("[edges] c2 1024x1024 u16")
+    f = synth.config2()
+    f = synth.Frame(f.image, f.cx, f.cy, f.R, f.s, f.A, dict(f.params, measure=O.MEASURE_EDGE, k_threshold=-12.0), 0)
+    _check_edge_measure(det, f)
+    ref, got, n = _ridge_sets(det, f)
+    sym = set(ref) ^ set(got)
+    say(f"  oracle {len(ref)} edge pixels, gpu {len(got)}, mismatched {len(sym)}")
+    assert len(sym) <= 1e-4 * len(ref)
+    ring_ref, ring_got, n_common, unmatched = _end_to_end(det, f, torch.from_numpy(f.image).cuda())
+    say(f"  rings: oracle {len(ring_ref)} gpu {len(ring_got)} matched {n_common} unmatched {unmatched}")
+    assert unmatched <= max(1, 0.01 * len(ring_ref))
+
+
+def test_edge_measure_rejected_by_the_differentiable_path(det):
+    from paper_1310_1371_amd.native import RdError
+    f = _edge_disc()
+    with pytest.raises(RdError):
+        det.soft_ridges(torch.from_numpy(f.image).cuda(), f.params)
+
+
 def test_wide_frame_beyond_2048_columns():
     """A 5000 x 48 float32 strip (coordinates past 4095 in the packed 16-bit ridge records),
     with rings along it: accumulator and scores bit-exact from the oracle's ridges, and the
