@@ -61,6 +61,28 @@ def test_rings_come_out_sorted(bdet):
         assert all(k0 < k1 for k0, k1 in zip(keys, keys[1:]))
 
 
+def test_edge_batch_equals_per_frame_and_modes_alternate(bdet):
+    """Directed edges through the batched path equal per-frame edge detections, and
+    alternating the measure between calls (each a different captured graph) gives each
+    mode's own rings back unchanged."""
+    say("[batch] directed edges: 4 uneven u16 frames vs per-frame, modes alternating")
+    fs = _frames_u16()
+    p_ridge = fs[0].params
+    p_edge = dict(p_ridge, measure=1, k_threshold=-12.0)
+    frames = [torch.from_numpy(f.image).cuda() for f in fs]
+    ridge0 = bdet.detect_batch(frames, p_ridge)
+    edge0 = bdet.detect_batch(frames, p_edge)
+    for f, fr, got in zip(fs, frames, edge0):
+        ref = bdet.detect(fr, p_edge)
+        assert _same(ref, got), (f.image.shape, len(ref), len(got))
+        say(f"  {f.image.shape}: {len(got)} edge rings")
+    ridge1 = bdet.detect_batch(frames, p_ridge)
+    edge1 = bdet.detect_batch(frames, p_edge)
+    assert all(_same(a, b) for a, b in zip(ridge0, ridge1))
+    assert all(_same(a, b) for a, b in zip(edge0, edge1))
+    assert any(not _same(a, b) for a, b in zip(ridge0, edge0))
+
+
 def test_batch_graph_replay_uses_new_data(bdet):
     say("[batch] graph replay with new frame contents")
     bdet.set_tuning(use_graph=True)
