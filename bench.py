@@ -18,7 +18,9 @@ Also reported, on the same GPU:
     detected ring, and the accuracy of refined vs algebraic-fit rings against the truth;
   - stream: a slice of the 2048^2 uint16 sequence with 1000 moving rings, 32 frames per
     launch, host-to-device copies overlapped on a second stream, refinement of all
-    detections;
+    detections, linking of the refined rings into tracks with depths, link accuracy against
+    the generator's truth;
+  - edges: the plain step with directed edges (gradient magnitude) on the headline frame;
   - the dominant kernel's roofline figures;
   - the CPU oracle timed on a bounded sample of the headline workload.
 
@@ -422,7 +424,10 @@ def differentiable(det, args, np, torch, synth):
 
 
 def stream(det, args, np, torch, synth):
-    """32 frames per launch; copies of launch k+1 overlap launch k on a second stream."""
+    """32 frames per launch; copies of launch k+1 overlap launch k on a second stream.  Each
+    launch: detection, 20 LM steps per ring, then the refined rings linked into tracks with
+    depths on the GPU.  Link accuracy is scored against the generator's truth afterwards."""
+    from paper_1310_1371_amd.tracking import Linker
     st = synth.Stream(seed=4)
     n = 32 * args.stream_launches
     host = pool_map(st.frame, list(range(n)))
@@ -446,6 +451,8 @@ def stream(det, args, np, torch, synth):
         e.record(main)
     n_rings = n_refined = 0
     t_first = None
+    linker = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32)
+    linked, t_link = [], 0.0
     issue_copy(0)
     for k in range(args.stream_launches):
         if k + 1 < args.stream_launches:
@@ -457,6 +464,13 @@ def stream(det, args, np, torch, synth):
                                .astype(np.float64)).cuda()
         fo = torch.cat([torch.full((len(r),), i, dtype=torch.int32, device="cuda") for i, r in enumerate(res)])
         theta, _ = det.refine(bufs[b], th0, 1.5, iters=20, frame_of=fo)
+        offs = np.zeros(33, dtype=np.int32)
+        offs[1:] = np.cumsum([len(r) for r in res])
+        tl0 = time.perf_counter()
+        ids, z = linker.link(theta.float().contiguous(), offs)
+        if k > 0:
+            t_link += time.perf_counter() - tl0
+        linked.append((theta.float(), ids, z, offs))
         released[b].record(main)
         n_rings += int(th0.shape[0])
         if k == 0:
@@ -465,11 +479,49 @@ def stream(det, args, np, torch, synth):
     torch.cuda.synchronize()
     timed = args.stream_launches - 1
     dt = (time.perf_counter() - t_first) / max(timed, 1)
+    tracks = linker.info()["tracks"]
+    linker.close()
+    acc = link_accuracy(np, linked, host)
     return {"frames": n, "launches_timed": timed, "frames_per_s": 32 / dt if timed else None,
             "value": 32 * 2048 * 2048 / dt / 1e6 if timed else None, "unit": "Mpixel/s",
             "ms_per_launch": dt * 1e3 if timed else None, "rings_detected_and_refined": n_rings,
+            "ms_link_per_launch": t_link / max(timed, 1) * 1e3, "tracks": tracks, "linking": acc,
             "workload": "2048^2 u16 stream, 1000 rings on random walks, radii 8-80, 32 frames per launch, "
-                        "H2D on a second stream, 20 LM steps per detection"}
+                        "H2D on a second stream, 20 LM steps per detection, linking (gate 8 px, memory 2) "
+                        "and depth on the GPU"}
+
+
+def link_accuracy(np, linked, host):
+    """Each detection is given the truth ring whose centre is nearest (within 3 px, radius
+    within 3 px); a link (consecutive detections of one track) is right when both ends have
+    the same truth ring."""
+    from scipy.spatial import cKDTree
+    xs, ids, zs, frame = [], [], [], []
+    f0 = 0
+    for th, i, z, offs in linked:
+        xs.append(th.cpu().numpy())
+        ids.append(i.cpu().numpy())
+        zs.append(z.cpu().numpy())
+        frame.append(f0 + np.repeat(np.arange(len(offs) - 1), np.diff(offs)))
+        f0 += len(offs) - 1
+    x, ids, z, frame = np.concatenate(xs), np.concatenate(ids), np.concatenate(zs), np.concatenate(frame)
+    truth = np.full(len(x), -1)
+    z_true = np.full(len(x), np.nan)
+    for f in range(f0):
+        sel = np.nonzero(frame == f)[0]
+        h = host[f]
+        d, j = cKDTree(np.stack([h.cx, h.cy], 1)).query(x[sel, :2])
+        ok = (d < 3.0) & (np.abs(h.R[j] - x[sel, 2]) < 3.0)
+        truth[sel[ok]] = j[ok]
+        z_true[sel[ok]] = np.sqrt((h.R[j[ok]] - 8.0) / 72.0)
+    order = np.lexsort((frame, ids))
+    same = ids[order][1:] == ids[order][:-1]
+    a, b = truth[order][:-1][same], truth[order][1:][same]
+    right = (a == b) & (a >= 0)
+    return {"links": int(same.sum()), "links_right": float(right.mean()) if same.any() else None,
+            "detections_matched_to_truth": float((truth >= 0).mean()),
+            "depth_mean_abs_err": float(np.nanmean(np.abs(z - z_true))),
+            "tracks_per_truth_ring": float(len(np.unique(ids)) / len(host[0].cx))}
 
 
 if __name__ == "__main__":

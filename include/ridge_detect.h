@@ -312,6 +312,65 @@ rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes,
                     const int32_t* frame_of_dev, const double* theta0_dev, int64_t m, double s,
                     int32_t iters, double* theta_dev, double* loss_dev);
 
+/* ---- linking rings into trajectories, depth from radius ------------------------------
+ *
+ * The paper follows particles by linking each frame's rings to the previous frames' with a
+ * predictive nearest-neighbour tracker that remembers missed particles for a few frames
+ * (Methods, "Experimental details"), and turns a ring's radius into depth with the larger
+ * root of a quadratic fit of radius against defocus (SI, calibration curve figure).  It
+ * does not print the tracker; this one is (all arithmetic in float32, rounded per
+ * operation, except the depth, float64 rounded to float32 once):
+ *   - a track keeps its last position p = (x, y, r), a velocity v (zero until its second
+ *     detection) and the frame t_l it was last seen in; ids are 0, 1, 2, ... by creation;
+ *   - it takes part in frame t while t - t_l <= memory + 1, and is retired after that;
+ *   - prediction p^ = p + v g with g = t - t_l; cost c = (x^-x)^2 + (y^-y)^2 + (r^-r)^2;
+ *     candidates c <= gate^2;
+ *   - greedy matching: candidates in increasing (c, track id, detection index) order, each
+ *     taken when both of its ends are still free;
+ *   - a matched track gets v = (d - p) / g, p = d, t_l = t; each unmatched detection opens a
+ *     track (v = 0), ids in increasing detection order;
+ *   - depth z(r) = larger root of c2 z^2 + c1 z + c0 - r = 0 for c2 > 0, the discriminant
+ *     clamped at 0. */
+
+#define RD_LINK_MAX_DETECTIONS 4096   /* detections in one frame                    */
+#define RD_LINK_MAX_ACTIVE 6144       /* tracks taking part in one frame            */
+
+typedef struct {
+    float gate;        /* > 0: largest distance in (x, y, r) space of a link, px        */
+    int32_t memory;    /* >= 0: frames a track may miss and still be continued          */
+    double depth_c0;   /* radius calibration r(z) = c0 + c1 z + c2 z^2, c2 > 0          */
+    double depth_c1;
+    double depth_c2;
+} rd_link_params;
+
+typedef struct rd_linker_s* rd_linker;
+
+/* A linker: device state for up to max_tracks tracks over the whole sequence and calls of
+ * up to max_frames frames.  Work is ordered on `stream` (hipStream_t; NULL = default) on the
+ * current device.  RD_E_INVALID for bad parameters, RD_E_NOMEM if allocation fails. */
+rd_status rd_linker_create(const rd_link_params* params, int32_t max_tracks, int32_t max_frames,
+                           void* stream, rd_linker* out);
+void rd_linker_destroy(rd_linker linker);
+
+/* Forget every track; the next frame is frame 0 again. */
+rd_status rd_linker_reset(rd_linker linker);
+
+/* Tracks opened so far, tracks taking part in the next frame, frames linked so far.
+ * RD_E_OVERFLOW if a capacity was exceeded since the last reset (the state is then
+ * invalid until rd_linker_reset). */
+rd_status rd_linker_info(rd_linker linker, int32_t* ntracks, int32_t* nactive, int32_t* frame);
+
+/* Link the next nframes frames (1 <= nframes <= max_frames).  det_dev: float32 (x, y, r)
+ * triples, device, frames back to back; frame_offsets: host, nframes + 1 prefix offsets
+ * into det_dev in detections, starting at 0, each frame <= RD_LINK_MAX_DETECTIONS
+ * (RD_E_TOO_LARGE otherwise).  Writes ids_dev[k] (int32, device) = the track id of
+ * detection k, and, if z_dev (float32, device) is not NULL, its depth.  Completed on
+ * return.  RD_E_OVERFLOW if more than max_tracks tracks, RD_LINK_MAX_ACTIVE tracks taking
+ * part in a frame, or 2^20 candidate pairs in a frame were needed: ids past that point
+ * are -1. */
+rd_status rd_link(rd_linker linker, const float* det_dev, const int32_t* frame_offsets,
+                  int32_t nframes, int32_t* ids_dev, float* z_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,341 @@
+// Frame-to-frame linking of detected rings into trajectories, and depth from radius.
+//
+// The paper links its per-frame ring lists with a predictive nearest-neighbour tracker that
+// has a memory for missed frames (Methods, "Experimental details"), and converts a ring's
+// radius into depth through the larger root of a quadratic calibration (SI, calibration
+// curve figure).  The tracker itself is not printed; the one here:
+//   prediction p^ = p + v g (g = frames since the track was last seen), cost
+//   c = |p^ - d|^2 over (x, y, r), candidates c <= gate^2, and the greedy matching that takes
+//   candidates in increasing (c, track id, detection index) order.
+//
+// The greedy matching is found without sorting: with a strict total order on the candidate
+// pairs, the greedy result is the union of rounds of "locally dominant" pairs, each pair the
+// smallest at both of its ends among the pairs still free (a classical property of greedy
+// matching).  Every round is two passes of LDS atomicMin over the candidate list, with
+// 64-bit keys (cost bits << 32 | other end) that order exactly as (c, i, j).  The cost is
+// float32, and non-negative, so its bit pattern orders like its value.
+//
+// One workgroup walks the frames in order (each frame depends on the previous one).  The
+// frame's detections sit in LDS; each thread scans them for its tracks' candidates.  Track
+// state lives in device memory between calls.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "ridge_detect.h"
+
+#define RD_LINK_HIP(call)                              \
+    do {                                               \
+        if ((call) != hipSuccess) return RD_E_DEVICE;  \
+    } while (0)
+
+namespace rd_track {
+
+constexpr int THREADS = 1024;
+constexpr int MAX_DET = RD_LINK_MAX_DETECTIONS;   // detections of one frame
+constexpr int MAX_ACTIVE = RD_LINK_MAX_ACTIVE;    // tracks taking part in one frame
+constexpr uint64_t FREE = ~0ull;
+
+enum { S_NTRACKS = 0, S_NACTIVE, S_FRAME, S_CUR, S_ERR, S_COUNT };
+enum { ERR_ACTIVE = 1, ERR_TRACKS = 2, ERR_EDGES = 4 };
+
+struct Args {
+    const float* det;          // 3 floats (x, y, r) per detection, frames back to back
+    const int32_t* offsets;    // nframes + 1 prefix offsets into det
+    int32_t nframes;
+    int32_t* ids;              // out: track id per detection (-1 after an overflow)
+    float* z;                  // out: depth per detection, or null
+    double c0, c1, c2;
+    float gate;
+    int32_t memory;
+    float* pos;                // 3 floats per track: last (x, y, r)
+    float* vel;                // 3 floats per track
+    int32_t* t_last;           // per track
+    int32_t* act0;             // active lists, double-buffered across frames
+    int32_t* act1;
+    int32_t* state;            // S_COUNT words
+    int32_t max_tracks;
+    uint4* edges;              // candidate pairs of one frame: (cost bits, slot, det, id)
+    int32_t max_edges;
+};
+
+__device__ inline uint64_t key(uint32_t cbits, uint32_t other) { return (uint64_t(cbits) << 32) | other; }
+
+__global__ __launch_bounds__(THREADS) void k_link(Args A) {
+#pragma clang fp contract(off)
+    __shared__ float4 sd[MAX_DET];                      // detection (x, y, r, -)
+    __shared__ unsigned long long bt[MAX_ACTIVE];       // best key per active slot
+    __shared__ unsigned long long bd[MAX_DET];          // best key per detection
+    __shared__ int16_t md[MAX_DET];                     // matched slot + 1, 0 = free
+    __shared__ uint8_t mt[MAX_ACTIVE];                  // slot matched
+    __shared__ int32_t s_ne, s_keep, s_changed, s_err, s_wave[THREADS / 64], s_base;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int ntracks = A.state[S_NTRACKS], nact = A.state[S_NACTIVE], t = A.state[S_FRAME];
+    int cur = A.state[S_CUR];
+    if (tid == 0) s_err = A.state[S_ERR];
+    const float g2 = A.gate * A.gate;
+
+    for (int f = 0; f < A.nframes; ++f) {
+        const int d0 = A.offsets[f], n = A.offsets[f + 1] - d0;   // n <= MAX_DET, checked on the host
+        const int32_t* act_in = cur ? A.act1 : A.act0;
+        int32_t* act_out = cur ? A.act0 : A.act1;
+        for (int j = tid; j < n; j += THREADS) {
+            const float* p = A.det + 3 * (int64_t)(d0 + j);
+            sd[j] = make_float4(p[0], p[1], p[2], 0.f);
+            bd[j] = FREE;
+            md[j] = 0;
+        }
+        if (tid == 0) { s_ne = 0; s_keep = 0; s_changed = 0; }
+        __syncthreads();
+
+        // Tracks still taking part keep a slot in the next active list and emit candidates.
+        for (int a = tid; a < nact; a += THREADS) {
+            const int i = act_in[a];
+            const int gap = t - A.t_last[i];
+            if (gap > A.memory + 1) continue;               // retired
+            const int slot = atomicAdd(&s_keep, 1);
+            if (slot >= MAX_ACTIVE) { atomicOr(&s_err, ERR_ACTIVE); continue; }
+            act_out[slot] = i;
+            const float g = (float)gap;
+            const float px = A.pos[3 * i] + A.vel[3 * i] * g;
+            const float py = A.pos[3 * i + 1] + A.vel[3 * i + 1] * g;
+            const float pr = A.pos[3 * i + 2] + A.vel[3 * i + 2] * g;
+            for (int j = 0; j < n; ++j) {
+                const float4 d = sd[j];
+                const float dx = px - d.x, dy = py - d.y, dr = pr - d.z;
+                const float c = dx * dx + dy * dy + dr * dr;
+                if (c <= g2) {
+                    const int e = atomicAdd(&s_ne, 1);
+                    if (e < A.max_edges) A.edges[e] = make_uint4(__float_as_uint(c), slot, j, i);
+                    else atomicOr(&s_err, ERR_EDGES);
+                }
+            }
+        }
+        __syncthreads();
+        const int keep = min(s_keep, MAX_ACTIVE);
+        const int ne = min(s_ne, A.max_edges);
+        for (int a = tid; a < keep; a += THREADS) { bt[a] = FREE; mt[a] = 0; }
+
+        // Rounds of locally dominant pairs.  Every round with a free candidate matches at
+        // least the smallest free one, so the loop ends after at most ne + 1 rounds.
+        for (;;) {
+            __syncthreads();
+            for (int e = tid; e < ne; e += THREADS) {
+                const uint4 E = A.edges[e];
+                if (mt[E.y] || md[E.z]) continue;
+                atomicMin(&bt[E.y], key(E.x, E.z));
+                atomicMin(&bd[E.z], key(E.x, E.w));
+            }
+            __syncthreads();
+            for (int e = tid; e < ne; e += THREADS) {
+                const uint4 E = A.edges[e];
+                if (mt[E.y] || md[E.z]) continue;
+                if (bt[E.y] == key(E.x, E.z) && bd[E.z] == key(E.x, E.w)) {
+                    mt[E.y] = 1;
+                    md[E.z] = (int16_t)(E.y + 1);
+                    s_changed = 1;
+                }
+            }
+            __syncthreads();
+            const int changed = s_changed;
+            __syncthreads();
+            if (!changed) break;
+            for (int a = tid; a < keep; a += THREADS)
+                if (!mt[a]) bt[a] = FREE;
+            for (int j = tid; j < n; j += THREADS)
+                if (!md[j]) bd[j] = FREE;
+            if (tid == 0) s_changed = 0;
+        }
+
+        // Matched tracks move; unmatched detections open tracks, ids by detection index.
+        if (tid == 0) s_base = 0;
+        __syncthreads();
+        for (int j0 = 0; j0 < n; j0 += THREADS) {
+            const int j = j0 + tid;
+            const bool fresh = j < n && md[j] == 0;
+            const uint64_t bal = __ballot(fresh);
+            if (lane == 0) s_wave[wave] = __popcll(bal);
+            __syncthreads();
+            int before = s_base;
+            for (int w = 0; w < wave; ++w) before += s_wave[w];
+            before += __popcll(bal & ((1ull << lane) - 1));
+            if (j < n) {
+                const float4 d = sd[j];
+                int id;
+                if (!fresh) {
+                    id = act_out[(int)md[j] - 1];
+                    const float g = (float)(t - A.t_last[id]);
+                    A.vel[3 * id] = (d.x - A.pos[3 * id]) / g;
+                    A.vel[3 * id + 1] = (d.y - A.pos[3 * id + 1]) / g;
+                    A.vel[3 * id + 2] = (d.z - A.pos[3 * id + 2]) / g;
+                } else {
+                    id = ntracks + before;
+                    const int slot = keep + before;
+                    if (id >= A.max_tracks) { atomicOr(&s_err, ERR_TRACKS); id = -1; }
+                    else if (slot >= MAX_ACTIVE) { atomicOr(&s_err, ERR_ACTIVE); id = -1; }
+                    else {
+                        act_out[slot] = id;
+                        A.vel[3 * id] = 0.f;
+                        A.vel[3 * id + 1] = 0.f;
+                        A.vel[3 * id + 2] = 0.f;
+                    }
+                }
+                if (id >= 0) {
+                    A.pos[3 * id] = d.x;
+                    A.pos[3 * id + 1] = d.y;
+                    A.pos[3 * id + 2] = d.z;
+                    A.t_last[id] = t;
+                }
+                A.ids[d0 + j] = id;
+                if (A.z) {
+                    const double disc = fmax(A.c1 * A.c1 - 4.0 * A.c2 * (A.c0 - (double)d.z), 0.0);
+                    A.z[d0 + j] = (float)((-A.c1 + sqrt(disc)) / (2.0 * A.c2));
+                }
+            }
+            __syncthreads();
+            if (tid == 0) for (int w = 0; w < THREADS / 64; ++w) s_base += s_wave[w];
+            __syncthreads();   // s_wave is rewritten by the next step
+        }
+        __syncthreads();
+        const int nnew = s_base;
+        ntracks = min(ntracks + nnew, A.max_tracks);
+        nact = min(keep + nnew, MAX_ACTIVE);
+        t += 1;
+        cur ^= 1;
+        __syncthreads();   // act_out, positions and LDS reuse ordered before the next frame
+    }
+    if (tid == 0) {
+        A.state[S_NTRACKS] = ntracks;
+        A.state[S_NACTIVE] = nact;
+        A.state[S_FRAME] = t;
+        A.state[S_CUR] = cur;
+        A.state[S_ERR] = s_err;
+    }
+}
+
+}  // namespace rd_track
+
+using namespace rd_track;
+
+struct rd_linker_s {
+    rd_link_params p{};
+    int32_t max_tracks = 0, max_edges = 0;
+    hipStream_t stream = nullptr;
+    float *pos = nullptr, *vel = nullptr;
+    int32_t *t_last = nullptr, *act0 = nullptr, *act1 = nullptr, *state = nullptr, *offsets = nullptr;
+    uint4* edges = nullptr;
+    int32_t max_frames = 0;
+    int32_t* h_state = nullptr;   // pinned
+};
+
+static void linker_free(rd_linker_s* L) {
+    (void)hipFree(L->pos); (void)hipFree(L->vel); (void)hipFree(L->t_last); (void)hipFree(L->act0); (void)hipFree(L->act1);
+    (void)hipFree(L->state); (void)hipFree(L->offsets); (void)hipFree(L->edges);
+    if (L->h_state) (void)hipHostFree(L->h_state);
+    delete L;
+}
+
+static bool link_params_ok(const rd_link_params* p) {
+    return p && p->gate > 0.f && p->gate < 1e18f && p->memory >= 0 && p->memory < (1 << 20) &&
+           p->depth_c2 != 0.0 && p->depth_c2 == p->depth_c2 && p->depth_c1 == p->depth_c1 &&
+           p->depth_c0 == p->depth_c0;
+}
+
+extern "C" rd_status rd_linker_create(const rd_link_params* params, int32_t max_tracks,
+                                      int32_t max_frames, void* stream, rd_linker* out) {
+    if (!out || !link_params_ok(params) || max_tracks < 1 || max_tracks > (1 << 28) || max_frames < 1 ||
+        max_frames > (1 << 20))
+        return RD_E_INVALID;
+    *out = nullptr;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return RD_E_DEVICE;
+    auto* L = new rd_linker_s;
+    L->p = *params;
+    L->max_tracks = max_tracks;
+    L->max_frames = max_frames;
+    L->max_edges = 1 << 20;
+    L->stream = (hipStream_t)stream;
+    const size_t nt = (size_t)max_tracks;
+    if (hipMalloc(&L->pos, nt * 3 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&L->vel, nt * 3 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&L->t_last, nt * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&L->act0, MAX_ACTIVE * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&L->act1, MAX_ACTIVE * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&L->state, S_COUNT * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&L->offsets, ((size_t)max_frames + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&L->edges, (size_t)L->max_edges * sizeof(uint4)) != hipSuccess ||
+        hipHostMalloc(&L->h_state, S_COUNT * sizeof(int32_t)) != hipSuccess) {
+        linker_free(L);
+        return RD_E_NOMEM;
+    }
+    if (hipMemsetAsync(L->state, 0, S_COUNT * sizeof(int32_t), L->stream) != hipSuccess ||
+        hipStreamSynchronize(L->stream) != hipSuccess) {
+        linker_free(L);
+        return RD_E_DEVICE;
+    }
+    *out = L;
+    return RD_OK;
+}
+
+extern "C" void rd_linker_destroy(rd_linker L) {
+    if (!L) return;
+    (void)hipStreamSynchronize(L->stream);
+    linker_free(L);
+}
+
+extern "C" rd_status rd_linker_reset(rd_linker L) {
+    if (!L) return RD_E_INVALID;
+    RD_LINK_HIP(hipMemsetAsync(L->state, 0, S_COUNT * sizeof(int32_t), L->stream));
+    RD_LINK_HIP(hipStreamSynchronize(L->stream));
+    return RD_OK;
+}
+
+extern "C" rd_status rd_linker_info(rd_linker L, int32_t* ntracks, int32_t* nactive, int32_t* frame) {
+    if (!L) return RD_E_INVALID;
+    RD_LINK_HIP(hipMemcpyAsync(L->h_state, L->state, S_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, L->stream));
+    RD_LINK_HIP(hipStreamSynchronize(L->stream));
+    if (ntracks) *ntracks = L->h_state[S_NTRACKS];
+    if (nactive) *nactive = L->h_state[S_NACTIVE];
+    if (frame) *frame = L->h_state[S_FRAME];
+    return L->h_state[S_ERR] ? RD_E_OVERFLOW : RD_OK;
+}
+
+extern "C" rd_status rd_link(rd_linker L, const float* det_dev, const int32_t* frame_offsets,
+                             int32_t nframes, int32_t* ids_dev, float* z_dev) {
+    if (!L || !frame_offsets || nframes < 1 || nframes > L->max_frames) return RD_E_INVALID;
+    if (frame_offsets[0] != 0) return RD_E_INVALID;
+    for (int f = 0; f < nframes; ++f) {
+        const int64_t n = (int64_t)frame_offsets[f + 1] - frame_offsets[f];
+        if (n < 0) return RD_E_INVALID;
+        if (n > MAX_DET) return RD_E_TOO_LARGE;
+    }
+    if (frame_offsets[nframes] > 0 && (!det_dev || !ids_dev)) return RD_E_INVALID;
+    RD_LINK_HIP(hipMemcpyAsync(L->offsets, frame_offsets, ((size_t)nframes + 1) * sizeof(int32_t),
+                               hipMemcpyHostToDevice, L->stream));
+    Args a{};
+    a.det = det_dev;
+    a.offsets = L->offsets;
+    a.nframes = nframes;
+    a.ids = ids_dev;
+    a.z = z_dev;
+    a.c0 = L->p.depth_c0;
+    a.c1 = L->p.depth_c1;
+    a.c2 = L->p.depth_c2;
+    a.gate = L->p.gate;
+    a.memory = L->p.memory;
+    a.pos = L->pos;
+    a.vel = L->vel;
+    a.t_last = L->t_last;
+    a.act0 = L->act0;
+    a.act1 = L->act1;
+    a.state = L->state;
+    a.max_tracks = L->max_tracks;
+    a.edges = L->edges;
+    a.max_edges = L->max_edges;
+    hipLaunchKernelGGL(k_link, dim3(1), dim3(THREADS), 0, L->stream, a);
+    RD_LINK_HIP(hipGetLastError());
+    return rd_linker_info(L, nullptr, nullptr, nullptr);
+}

@@ -43,6 +43,11 @@ class RdTuning(ctypes.Structure):
     _fields_ = [("stencil_tile", ctypes.c_int32), ("vote_lds_kb", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
+class RdLinkParams(ctypes.Structure):
+    _fields_ = [("gate", ctypes.c_float), ("memory", ctypes.c_int32), ("depth_c0", ctypes.c_double),
+                ("depth_c1", ctypes.c_double), ("depth_c2", ctypes.c_double)]
+
+
 class RdError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -82,6 +87,11 @@ SIGNATURES = {
     "rd_fit_loss": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp]),
     "rd_fit_loss_backward": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp, _vp]),
     "rd_refine": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _vp, _vp, _i64, ctypes.c_double, _i32, _vp, _vp]),
+    "rd_linker_create": (ctypes.c_int, [_P(RdLinkParams), _i32, _i32, _vp, _P(_vp)]),
+    "rd_linker_destroy": (None, [_vp]),
+    "rd_linker_reset": (ctypes.c_int, [_vp]),
+    "rd_linker_info": (ctypes.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32)]),
+    "rd_link": (ctypes.c_int, [_vp, _vp, _P(_i32), _i32, _vp, _vp]),
 }
 
 _lib = None

@@ -98,3 +98,16 @@ def test_create_without_gpu_reports_device_error():
     bad = N.RdCreateInfo(0, 16, 256, 1024, 1, 0, None)
     assert lib.rd_create(ctypes.byref(bad), ctypes.byref(h)) == N.RD_E_INVALID
     lib.rd_destroy(None)
+
+
+@pytest.mark.parametrize("gate,memory,c2,max_tracks", [
+    (0.0, 1, 72.0, 100), (-1.0, 1, 72.0, 100), (float("nan"), 1, 72.0, 100), (5.0, -1, 72.0, 100),
+    (5.0, 1, 0.0, 100), (5.0, 1, float("nan"), 100), (5.0, 1, 72.0, 0)])
+def test_linker_parameters_are_validated_before_device_work(gate, memory, c2, max_tracks):
+    lib = _ensure_built()
+    h = ctypes.c_void_p()
+    p = N.RdLinkParams(gate, memory, 8.0, 0.0, c2)
+    assert lib.rd_linker_create(ctypes.byref(p), max_tracks, 4, None, ctypes.byref(h)) == N.RD_E_INVALID
+    offs = (ctypes.c_int32 * 2)(0, 0)
+    assert lib.rd_link(None, None, offs, 1, None, None) == N.RD_E_INVALID
+    assert lib.rd_linker_reset(None) == N.RD_E_INVALID

@@ -1,0 +1,149 @@
+"""Linking on the GPU against the tracking oracle: every track id bit-exact, depths equal to
+the oracle's float64 value rounded to float32, across calls, resets, empty frames, the
+largest frame and the capacity errors."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import track as T
+
+pytestmark = pytest.mark.gpu
+
+f32 = np.float32
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _walk_frames(seed, n, n_frames, W=2048.0, noise=0.3, drop=0.05, spurious=20):
+    """Particles on the stream's random walks (1.5 px per frame in x and y, depth 0.01 per
+    frame, r = 8 + 72 z^2), seen with Gaussian position noise, dropouts and spurious
+    detections, in shuffled order."""
+    rng = np.random.default_rng(seed)
+    x, y, z = rng.uniform(0, W, n), rng.uniform(0, W, n), rng.uniform(0, 1, n)
+    frames = []
+    for _ in range(n_frames):
+        x, y = x + rng.normal(0, 1.5, n), y + rng.normal(0, 1.5, n)
+        z = np.clip(z + rng.normal(0, 0.01, n), 0, 1)
+        keep = rng.random(n) > drop
+        d = np.stack([x, y, 8 + 72 * z * z], 1)[keep] + rng.normal(0, noise, (keep.sum(), 3))
+        s = np.stack([rng.uniform(0, W, spurious), rng.uniform(0, W, spurious), rng.uniform(8, 80, spurious)], 1)
+        d = np.concatenate([d, s])
+        frames.append(d[rng.permutation(len(d))].astype(f32))
+    return frames
+
+
+def _lattice_frames(seed, n, n_frames, box=64):
+    """Crowded integer coordinates: many equal costs, so the order of ties decides."""
+    rng = np.random.default_rng(seed)
+    p = rng.integers(0, box, (n, 2)).astype(np.float64)
+    frames = []
+    for _ in range(n_frames):
+        p += rng.integers(-2, 3, p.shape)
+        keep = rng.random(n) > 0.1
+        r = 10.0 + (np.arange(n) % 4)
+        d = np.concatenate([p, r[:, None]], 1)[keep]
+        frames.append(d[rng.permutation(len(d))].astype(f32))
+    return frames
+
+
+def _pack(frames):
+    offs = np.zeros(len(frames) + 1, dtype=np.int32)
+    offs[1:] = np.cumsum([len(f) for f in frames])
+    det = np.concatenate(frames) if offs[-1] else np.zeros((0, 3), dtype=f32)
+    return torch.from_numpy(np.ascontiguousarray(det, dtype=f32)).cuda(), offs
+
+
+def _check(lk, tr, frames, depth=(8.0, 0.0, 72.0)):
+    det, offs = _pack(frames)
+    ids, z = lk.link(det, offs)
+    ref = np.concatenate([tr.link_frame(f) for f in frames]).astype(np.int64)
+    got = ids.cpu().numpy().astype(np.int64)
+    bad = int((got != ref).sum())
+    say(f"  {len(frames)} frames, {len(ref)} detections, {len(tr.p)} tracks; id mismatches {bad}")
+    assert bad == 0
+    if len(det):
+        zr = T.depth(det.cpu().numpy()[:, 2].astype(np.float64), *depth).astype(f32)
+        assert np.array_equal(z.cpu().numpy(), zr)
+
+
+@pytest.fixture
+def linker_cls():
+    from paper_1310_1371_amd.tracking import Linker
+    return Linker
+
+
+@pytest.mark.parametrize("gate,memory", [(8.0, 2), (4.0, 0)])
+def test_random_walks_over_two_calls(linker_cls, gate, memory):
+    say(f"[track] 1200 walking particles, 40 frames in calls of 25 + 15, gate {gate}, memory {memory}")
+    frames = _walk_frames(11, 1200, 40)
+    lk = linker_cls(gate, memory)
+    tr = T.Tracker(gate, memory)
+    _check(lk, tr, frames[:25])
+    _check(lk, tr, frames[25:])
+    info = lk.info()
+    assert info["frame"] == 40 and info["tracks"] == len(tr.p)
+    lk.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_crowded_lattice_ties(linker_cls, seed):
+    say(f"[track] crowded integer lattice, seed {seed}")
+    frames = _lattice_frames(seed, 300, 30)
+    lk = linker_cls(3.0, 1)
+    _check(lk, T.Tracker(3.0, 1), frames)
+    lk.close()
+
+
+def test_empty_frames_and_reset(linker_cls):
+    say("[track] empty frames, an all-empty call, reset")
+    frames = _walk_frames(5, 200, 12)
+    frames[3] = frames[3][:0]
+    frames[4] = frames[4][:0]
+    lk = linker_cls(8.0, 2)
+    tr = T.Tracker(8.0, 2)
+    _check(lk, tr, frames[:8])
+    _check(lk, tr, [frames[0][:0]] * 3)
+    _check(lk, tr, frames[8:])
+    lk.reset()
+    assert lk.info() == {"tracks": 0, "active": 0, "frame": 0}
+    _check(lk, T.Tracker(8.0, 2), frames[:5])
+    lk.close()
+
+
+def test_largest_frame(linker_cls):
+    """Two frames of 4096 detections (the per-frame maximum), the second the first moved by
+    half a pixel: every detection continues its track."""
+    say("[track] 2 x 4096 detections")
+    rng = np.random.default_rng(3)
+    g = np.stack(np.meshgrid(np.arange(64), np.arange(64)), -1).reshape(-1, 2) * 30.0
+    a = np.concatenate([g, rng.uniform(8, 80, (4096, 1))], 1).astype(f32)
+    b = (a + np.array([0.5, -0.5, 0.25])).astype(f32)
+    lk = linker_cls(5.0, 0, depth=(5.0, -3.0, 2.5))
+    tr = T.Tracker(5.0, 0)
+    _check(lk, tr, [a[rng.permutation(4096)], b[rng.permutation(4096)]], depth=(5.0, -3.0, 2.5))
+    assert lk.info()["tracks"] == 4096
+    lk.close()
+
+
+def test_capacity_errors(linker_cls):
+    from paper_1310_1371_amd.native import RdError, RD_E_TOO_LARGE, RD_E_OVERFLOW
+    say("[track] capacity errors: a frame above the maximum, too many tracks")
+    lk = linker_cls(5.0, 0, max_tracks=100)
+    det, offs = _pack([np.zeros((4097, 3), dtype=f32)])
+    with pytest.raises(RdError) as e:
+        lk.link(det, offs)
+    assert e.value.status == RD_E_TOO_LARGE
+    assert lk.info()["frame"] == 0
+    frames = _walk_frames(9, 150, 1, spurious=0)
+    det, offs = _pack(frames)
+    with pytest.raises(RdError) as e:
+        lk.link(det, offs)
+    assert e.value.status == RD_E_OVERFLOW
+    lk.reset()
+    _check(lk, T.Tracker(5.0, 0), [frames[0][:90]])
+    lk.close()
