@@ -62,20 +62,43 @@ struct Args {
 
 __device__ inline uint64_t key(uint32_t cbits, uint32_t other) { return (uint64_t(cbits) << 32) | other; }
 
+// Candidate search grid: square cells of side cs >= 1.125 gate hashed into NB buckets.  A
+// pair within the gate is at most gate (1 + 1e-6) apart along x and along y, under 0.89 cs,
+// so its cells differ by at most one even after the products v / cs are rounded (each off
+// by at most 2^-6 cells while |v| < 2^17 and cs >= 1/4).  Coordinates beyond that, and
+// non-finite ones, take the exhaustive scan instead, so the candidate set is always exactly
+// the pairs that pass the cost test.
+constexpr int NB = 4096;
+constexpr float NEAR = 131072.f;
+__device__ inline bool near(float v) { return fabsf(v) < NEAR; }
+__device__ inline int cell(float v, float inv_cs) { return (int)floorf(v * inv_cs); }
+__device__ inline int bucket(int cx, int cy) {
+    uint32_t h = (uint32_t)cx * 0x9E3779B1u ^ (uint32_t)cy * 0x85EBCA77u;
+    return (int)((h ^ (h >> 15)) & (NB - 1));
+}
+
 __global__ __launch_bounds__(THREADS) void k_link(Args A) {
 #pragma clang fp contract(off)
-    __shared__ float4 sd[MAX_DET];                      // detection (x, y, r, -)
+    __shared__ float sx[MAX_DET], sy[MAX_DET], sr[MAX_DET];   // detections
     __shared__ unsigned long long bt[MAX_ACTIVE];       // best key per active slot
     __shared__ unsigned long long bd[MAX_DET];          // best key per detection
     __shared__ int16_t md[MAX_DET];                     // matched slot + 1, 0 = free
     __shared__ uint8_t mt[MAX_ACTIVE];                  // slot matched
-    __shared__ int32_t s_ne, s_keep, s_changed, s_err, s_wave[THREADS / 64], s_base;
+    __shared__ int32_t s_ne, s_keep, s_changed, s_err, s_wave[THREADS / 64], s_base, s_far;
+    // The grid lives in bd's storage and its prefix scan in bt's: both are initialised only
+    // after the candidate search.  A detection's rank within its bucket waits in md.
+    uint32_t* gstart = reinterpret_cast<uint32_t*>(bd);                  // NB bucket starts
+    uint16_t* gidx = reinterpret_cast<uint16_t*>(gstart + NB);           // detections by bucket
+    int32_t* stmp = reinterpret_cast<int32_t*>(bt);                      // THREADS partial sums
+    static_assert(NB * 4 + MAX_DET * 2 <= MAX_DET * 8, "grid must fit in bd");
+    static_assert(THREADS * 4 <= MAX_ACTIVE * 8 && NB == 4 * THREADS, "scan layout");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int ntracks = A.state[S_NTRACKS], nact = A.state[S_NACTIVE], t = A.state[S_FRAME];
     int cur = A.state[S_CUR];
     if (tid == 0) s_err = A.state[S_ERR];
     const float g2 = A.gate * A.gate;
+    const float inv_cs = 1.0f / fmaxf(1.125f * A.gate, 0.25f);
 
     for (int f = 0; f < A.nframes; ++f) {
         const int d0 = A.offsets[f], n = A.offsets[f + 1] - d0;   // n <= MAX_DET, checked on the host
@@ -83,12 +106,39 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
         int32_t* act_out = cur ? A.act0 : A.act1;
         for (int j = tid; j < n; j += THREADS) {
             const float* p = A.det + 3 * (int64_t)(d0 + j);
-            sd[j] = make_float4(p[0], p[1], p[2], 0.f);
-            bd[j] = FREE;
-            md[j] = 0;
+            sx[j] = p[0];
+            sy[j] = p[1];
+            sr[j] = p[2];
         }
-        if (tid == 0) { s_ne = 0; s_keep = 0; s_changed = 0; }
+        for (int b = tid; b < NB; b += THREADS) gstart[b] = 0;
+        if (tid == 0) { s_ne = 0; s_keep = 0; s_changed = 0; s_far = 0; }
         __syncthreads();
+
+        // Counting sort of the detections into the grid's buckets.
+        for (int j = tid; j < n; j += THREADS) {
+            const float x = sx[j], y = sy[j];
+            if (near(x) && near(y)) md[j] = (int16_t)atomicAdd(&gstart[bucket(cell(x, inv_cs), cell(y, inv_cs))], 1u);
+            else { md[j] = -1; s_far = 1; }
+        }
+        __syncthreads();
+        uint32_t c4[4], run = 0;
+        for (int k = 0; k < 4; ++k) { c4[k] = gstart[4 * tid + k]; run += c4[k]; }
+        stmp[tid] = (int32_t)run;
+        __syncthreads();
+        for (int off = 1; off < THREADS; off <<= 1) {
+            const int32_t v = tid >= off ? stmp[tid - off] : 0;
+            __syncthreads();
+            stmp[tid] += v;
+            __syncthreads();
+        }
+        const int total = stmp[THREADS - 1];
+        run = (uint32_t)stmp[tid] - run;
+        for (int k = 0; k < 4; ++k) { gstart[4 * tid + k] = run; run += c4[k]; }
+        __syncthreads();
+        for (int j = tid; j < n; j += THREADS)
+            if (md[j] >= 0) gidx[gstart[bucket(cell(sx[j], inv_cs), cell(sy[j], inv_cs))] + md[j]] = (uint16_t)j;
+        __syncthreads();
+        const bool far_frame = s_far != 0;
 
         // Tracks still taking part keep a slot in the next active list and emit candidates.
         for (int a = tid; a < nact; a += THREADS) {
@@ -102,14 +152,30 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
             const float px = A.pos[3 * i] + A.vel[3 * i] * g;
             const float py = A.pos[3 * i + 1] + A.vel[3 * i + 1] * g;
             const float pr = A.pos[3 * i + 2] + A.vel[3 * i + 2] * g;
-            for (int j = 0; j < n; ++j) {
-                const float4 d = sd[j];
-                const float dx = px - d.x, dy = py - d.y, dr = pr - d.z;
+            auto test = [&](int j) {
+                const float dx = px - sx[j], dy = py - sy[j], dr = pr - sr[j];
                 const float c = dx * dx + dy * dy + dr * dr;
                 if (c <= g2) {
                     const int e = atomicAdd(&s_ne, 1);
                     if (e < A.max_edges) A.edges[e] = make_uint4(__float_as_uint(c), slot, j, i);
                     else atomicOr(&s_err, ERR_EDGES);
+                }
+            };
+            if (far_frame || !near(px) || !near(py)) {
+                for (int j = 0; j < n; ++j) test(j);
+            } else {
+                const int cx = cell(px, inv_cs), cy = cell(py, inv_cs);
+                int bs[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) bs[k] = bucket(cx + k % 3 - 1, cy + k / 3 - 1);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    bool dup = false;          // two cells hashed to one bucket: scan it once
+#pragma unroll
+                    for (int m = 0; m < k; ++m) dup |= bs[m] == bs[k];
+                    if (dup) continue;
+                    const int end = bs[k] + 1 < NB ? (int)gstart[bs[k] + 1] : total;
+                    for (int q = (int)gstart[bs[k]]; q < end; ++q) test(gidx[q]);
                 }
             }
         }
@@ -117,6 +183,7 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
         const int keep = min(s_keep, MAX_ACTIVE);
         const int ne = min(s_ne, A.max_edges);
         for (int a = tid; a < keep; a += THREADS) { bt[a] = FREE; mt[a] = 0; }
+        for (int j = tid; j < n; j += THREADS) { bd[j] = FREE; md[j] = 0; }
 
         // Rounds of locally dominant pairs.  Every round with a free candidate matches at
         // least the smallest free one, so the loop ends after at most ne + 1 rounds.
@@ -162,7 +229,7 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
             for (int w = 0; w < wave; ++w) before += s_wave[w];
             before += __popcll(bal & ((1ull << lane) - 1));
             if (j < n) {
-                const float4 d = sd[j];
+                const float4 d = make_float4(sx[j], sy[j], sr[j], 0.f);
                 int id;
                 if (!fresh) {
                     id = act_out[(int)md[j] - 1];
@@ -190,7 +257,8 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
                 }
                 A.ids[d0 + j] = id;
                 if (A.z) {
-                    const double disc = fmax(A.c1 * A.c1 - 4.0 * A.c2 * (A.c0 - (double)d.z), 0.0);
+                    double disc = A.c1 * A.c1 - 4.0 * A.c2 * (A.c0 - (double)d.z);
+                    disc = disc < 0.0 ? 0.0 : disc;          // a NaN radius stays NaN
                     A.z[d0 + j] = (float)((-A.c1 + sqrt(disc)) / (2.0 * A.c2));
                 }
             }

@@ -68,7 +68,7 @@ def _check(lk, tr, frames, depth=(8.0, 0.0, 72.0)):
     assert bad == 0
     if len(det):
         zr = T.depth(det.cpu().numpy()[:, 2].astype(np.float64), *depth).astype(f32)
-        assert np.array_equal(z.cpu().numpy(), zr)
+        assert np.array_equal(z.cpu().numpy(), zr, equal_nan=True)
 
 
 @pytest.fixture
@@ -112,6 +112,25 @@ def test_empty_frames_and_reset(linker_cls):
     lk.reset()
     assert lk.info() == {"tracks": 0, "active": 0, "frame": 0}
     _check(lk, T.Tracker(8.0, 2), frames[:5])
+    lk.close()
+
+
+def test_far_and_non_finite_coordinates(linker_cls):
+    """Detections far outside any frame (|x| >= 2^17, where the kernel's search grid gives
+    way to the exhaustive scan), some of them moving in from inside, and NaN or infinite
+    detections, which match nothing and open tracks of their own."""
+    say("[track] far and non-finite coordinates")
+    frames = _walk_frames(21, 300, 10)
+    rng = np.random.default_rng(4)
+    far = np.stack([131000.0 + 40.0 * np.arange(20), np.full(20, -5.0), np.full(20, 30.0)], 1)
+    out = []
+    for t, f in enumerate(frames):
+        extra = far + np.array([4.0 * t, 1.0 * t, 0.0])      # crosses x = 2^17 on the way
+        bad = np.array([[np.nan, 10.0, 10.0], [10.0, np.inf, 10.0], [5.0, 5.0, np.nan]])
+        d = np.concatenate([f, extra, bad]).astype(f32)
+        out.append(d[rng.permutation(len(d))])
+    lk = linker_cls(6.0, 1)
+    _check(lk, T.Tracker(6.0, 1), out)
     lk.close()
 
 
