@@ -451,7 +451,7 @@ def stream(det, args, np, torch, synth):
         e.record(main)
     n_rings = n_refined = 0
     t_first = None
-    linker = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32)
+    linker = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32, stream=det.stream)
     linked, t_link = [], 0.0
     issue_copy(0)
     for k in range(args.stream_launches):
@@ -466,11 +466,13 @@ def stream(det, args, np, torch, synth):
         theta, _ = det.refine(bufs[b], th0, 1.5, iters=20, frame_of=fo)
         offs = np.zeros(33, dtype=np.int32)
         offs[1:] = np.cumsum([len(r) for r in res])
+        dets = theta.float().contiguous()
+        torch.cuda.synchronize()      # rd_link returns completed anyway; this isolates its time
         tl0 = time.perf_counter()
-        ids, z = linker.link(theta.float().contiguous(), offs)
+        ids, z = linker.link(dets, offs)
         if k > 0:
             t_link += time.perf_counter() - tl0
-        linked.append((theta.float(), ids, z, offs))
+        linked.append((dets, ids, z, offs))
         released[b].record(main)
         n_rings += int(th0.shape[0])
         if k == 0:

@@ -16,8 +16,9 @@
 // float32, and non-negative, so its bit pattern orders like its value.
 //
 // One workgroup walks the frames in order (each frame depends on the previous one).  The
-// frame's detections sit in LDS; each thread scans them for its tracks' candidates.  Track
-// state lives in device memory between calls.
+// frame's detections sit in LDS, counting-sorted into a hashed grid of cells at least
+// 1.125 gate wide; each thread looks up its tracks' candidates in the 3 x 3 cells around the
+// prediction.  Track state lives in device memory between calls.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

@@ -290,6 +290,26 @@ def test_end_to_end_rings(det, name):
     assert unmatched <= max(1, 0.01 * len(ref))
 
 
+def test_ridge_list_is_a_lossless_representation(det):
+    """The ridge list (coordinates and direction codes) stands in for the frame: detection
+    from it gives the rings of rd_detect byte for byte, at 12 bytes per ridge (8 as 16-bit
+    fields) against 2 bytes per pixel of the u16 frame."""
+    say("[ridges] c2 1024x1024: rd_stage_ridges -> rd_detect_ridges vs rd_detect")
+    f = synth.config2()
+    frame = torch.from_numpy(f.image).cuda()
+    xy, q, _ = det.ridges(frame, f.params)
+    assert int(xy.max()) < 65536 and int(q.abs().max()) <= 1 << 14
+    from_list = det.detect_from_ridges(xy, q, f.width, f.height, f.params)
+    direct = det.detect(frame, f.params)
+    say(f"  {xy.shape[0]} ridges: {8 * xy.shape[0] / 2**20:.2f} MiB as 16-bit fields vs "
+        f"{f.image.nbytes / 2**20:.2f} MiB frame; {len(direct)} rings")
+    assert len(direct) > 100 and from_list.tobytes() == direct.tobytes()
+    # the order of the list does not matter
+    perm = torch.randperm(xy.shape[0], generator=torch.Generator().manual_seed(0)).cuda()
+    shuffled = det.detect_from_ridges(xy[perm], q[perm], f.width, f.height, f.params)
+    assert shuffled.tobytes() == direct.tobytes()
+
+
 # ---------------------------------------------------------------- directed edges
 
 def _edge_disc():

@@ -130,7 +130,8 @@ def test_far_and_non_finite_coordinates(linker_cls):
         d = np.concatenate([f, extra, bad]).astype(f32)
         out.append(d[rng.permutation(len(d))])
     lk = linker_cls(6.0, 1)
-    _check(lk, T.Tracker(6.0, 1), out)
+    with np.errstate(invalid="ignore"):
+        _check(lk, T.Tracker(6.0, 1), out)
     lk.close()
 
 
