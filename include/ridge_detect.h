@@ -215,9 +215,19 @@ rd_status rd_stage_ridges(rd_handle h, const rd_frame* frame, const rd_params* p
                           int32_t* xy_dev, int16_t* q_dev, float* k_dev,
                           int64_t capacity, int64_t* n_ridges);
 
+/* Host-only check of a ridge list (host arrays): every pixel inside the width x height frame
+ * and listed once, every direction code one that step 1 produces, i.e. rint(2^14 X_-) of a
+ * unit X_- in canonical sign: |qx^2 + qy^2 - 2^28| <= 2^15 and (qy > 0, or qy == 0 and
+ * qx > 0).  RD_OK or RD_E_INVALID.  rd_stage_accumulate and rd_detect_ridges apply the same
+ * test on the device.  These are the lists for which the integer votes are exact: a voxel at
+ * level r then takes at most one vote per lattice offset that the rounded r X_- can reach
+ * (about 8 r), far below the 16-bit counters and the 32-bit partial sums of the score. */
+rd_status rd_validate_ridges(const int32_t* xy, const int16_t* q, int64_t n, int32_t width, int32_t height);
+
 /* Step 3 (and the scores of step 4) from a caller-given ridge list: xy_dev = (x, y) int32
- * pairs and q_dev = (qx, qy) int16 pairs for n ridges (device pointers; at most 256
- * ridges per 16x16 bin, duplicates allowed within that).  acc_dev receives the dense vote
+ * pairs and q_dev = (qx, qy) int16 pairs for n ridges (device pointers; the list must pass
+ * the test of rd_validate_ridges, checked on the device: RD_E_INVALID otherwise; any order,
+ * e.g. the bin order of rd_stage_ridges or raster order).  acc_dev receives the dense vote
  * accumulator, uint32 [L][height][width] with L = r_max - r_min + 3 levels for radii
  * r_min - 1 .. r_max + 1.  score_dev (may be NULL) receives the integer smoothed score
  * S_int = sum W(|dx|) W(|dy|) A (W = 15-bit fixed-point Gaussian factors) at hotspots and
@@ -338,7 +348,8 @@ rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes,
 typedef struct {
     float gate;        /* > 0: largest distance in (x, y, r) space of a link, px        */
     int32_t memory;    /* >= 0: frames a track may miss and still be continued          */
-    double depth_c0;   /* radius calibration r(z) = c0 + c1 z + c2 z^2, c2 > 0          */
+    double depth_c0;   /* radius calibration r(z) = c0 + c1 z + c2 z^2; all finite and
+                          c2 > 0, else rd_linker_create returns RD_E_INVALID              */
     double depth_c1;
     double depth_c2;
 } rd_link_params;
@@ -366,8 +377,11 @@ rd_status rd_linker_info(rd_linker linker, int32_t* ntracks, int32_t* nactive, i
  * (RD_E_TOO_LARGE otherwise).  Writes ids_dev[k] (int32, device) = the track id of
  * detection k, and, if z_dev (float32, device) is not NULL, its depth.  Completed on
  * return.  RD_E_OVERFLOW if more than max_tracks tracks, RD_LINK_MAX_ACTIVE tracks taking
- * part in a frame, or 2^20 candidate pairs in a frame were needed: ids past that point
- * are -1. */
+ * part in a frame, or 2^20 candidate pairs in a frame were needed.  In the frame where that
+ * happens, the detections that could not open a track get id -1 (the others are linked, or
+ * open the tracks that still fit, in detection order); every later frame, in this call and
+ * the following ones, gets id -1 for all of its detections (depths are still written) until
+ * rd_linker_reset.  rd_linker_info then reports at most max_tracks tracks. */
 rd_status rd_link(rd_linker linker, const float* det_dev, const int32_t* frame_offsets,
                   int32_t nframes, int32_t* ids_dev, float* z_dev);
 

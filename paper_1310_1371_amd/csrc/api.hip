@@ -375,6 +375,7 @@ rd_status copy_rings(rd_ctx* h, int f, rd_ring* out, int32_t capacity, int32_t* 
 rd_status bin_external(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n, int W, int H) {
     const int nbx = (W + BIN - 1) / BIN, nby = (H + BIN - 1) / BIN;
     RD_HIP(hipMemsetAsync(h->d_bin_count, 0, static_cast<size_t>(nbx) * nby * sizeof(uint32_t), h->stream));
+    RD_HIP(hipMemsetAsync(h->d_pixmask, 0, static_cast<size_t>(nbx) * nby * 8 * sizeof(uint32_t), h->stream));
     uint32_t* d_flag = h->d_counts + h->max_frames;
     RD_HIP(hipMemsetAsync(d_flag, 0, sizeof(uint32_t), h->stream));
     BinArgs b{};
@@ -388,14 +389,15 @@ rd_status bin_external(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n
     b.rq = h->d_rq;
     b.rk = h->d_rk;
     b.bin_count = h->d_bin_count;
-    b.overflow = d_flag;
+    b.pixel_mask = h->d_pixmask;
+    b.flags = d_flag;
     RD_HIP(launch_bin(b, h->stream));
     uint32_t flag = 0;
     RD_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
-    if (flag & 2u) return RD_E_INVALID;
-    if (flag & 1u) return RD_E_OVERFLOW;
-    return RD_OK;
+    // off the frame, a code step 1 cannot make, a pixel listed twice (more than 256 in a bin
+    // implies a repeat)
+    return flag ? RD_E_INVALID : RD_OK;
 }
 
 rd_status ridge_setup(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n, int32_t W, int32_t H,
@@ -471,6 +473,21 @@ rd_status rd_validate_params(const rd_params* p) {
     return RD_OK;
 }
 
+rd_status rd_validate_ridges(const int32_t* xy, const int16_t* q, int64_t n, int32_t width, int32_t height) {
+    if (n < 0 || (n > 0 && (!xy || !q)) || width < 1 || height < 1 || width > MAX_DIM || height > MAX_DIM)
+        return RD_E_INVALID;
+    std::vector<uint8_t> seen((static_cast<size_t>(width) * height + 7) / 8, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int x = xy[2 * i], y = xy[2 * i + 1];
+        if (x < 0 || x >= width || y < 0 || y >= height) return RD_E_INVALID;
+        if (!ridge_code_ok(q[2 * i], q[2 * i + 1])) return RD_E_INVALID;
+        const size_t pix = static_cast<size_t>(y) * width + x;
+        if (seen[pix >> 3] & (1u << (pix & 7))) return RD_E_INVALID;
+        seen[pix >> 3] |= static_cast<uint8_t>(1u << (pix & 7));
+    }
+    return RD_OK;
+}
+
 rd_status rd_level_tables(const rd_params* p, int32_t capacity_levels, int32_t* ktab, uint32_t* wtab,
                           uint64_t* thr) {
     RD_TRY(rd_validate_params(p));
@@ -535,6 +552,7 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_thr), (R_LIMIT + 3) * sizeof(uint64_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_chunks), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_offsets), bins_single * sizeof(int64_t)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_pixmask), bins_single * 8 * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_rings), npk * sizeof(rd_ring), hipHostMallocMapped) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t),
                              hipHostMallocMapped) == hipSuccess;
@@ -574,6 +592,7 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_thr);
     (void)hipFree(h->d_chunks);
     (void)hipFree(h->d_offsets);
+    (void)hipFree(h->d_pixmask);
     for (hipEvent_t& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_rings) (void)hipHostFree(h->h_rings);

@@ -77,6 +77,7 @@ struct rd_ctx {
     uint64_t* d_thr = nullptr;
     int32_t* d_chunks = nullptr;
     int64_t* d_offsets = nullptr;       // stage gather offsets (per bin of one frame)
+    uint32_t* d_pixmask = nullptr;      // caller ridge lists: one bit per pixel of one frame's bins
     // pinned host memory; rings and counts are written by the fit kernel through mappings
     rd_ring* h_rings = nullptr;
     rd_ring* dh_rings = nullptr;

@@ -14,6 +14,20 @@ constexpr int BIN = 16;
 constexpr int BIN_SHIFT = 4;
 constexpr int BIN_CAP = BIN * BIN;
 
+// A caller-given ridge direction code must be what step 1 produces: rint(2^14 X_-) of a
+// unit vector, so |q|^2 lies within 2 * 2^14 * (|cos| + |sin|) / 2 + 1/2 <= 23171 of 2^28
+// (accepted: within 2^15), in canonical sign (qy > 0, or qy == 0 and qx > 0).  With such
+// codes and distinct pixels a voxel at level r takes at most one vote per lattice offset
+// that rho(r, q) can reach, which keeps the u16 vote counters and the 32-bit band sums of
+// the score exact.
+constexpr uint32_t Q_UNIT2 = 1u << 28;
+constexpr uint32_t Q_UNIT2_TOL = 1u << 15;
+__host__ __device__ inline bool ridge_code_ok(int qx, int qy) {
+    const uint32_t n2 = static_cast<uint32_t>(qx * qx) + static_cast<uint32_t>(qy * qy);   // <= 2^31
+    const uint32_t dev = n2 > Q_UNIT2 ? n2 - Q_UNIT2 : Q_UNIT2 - n2;
+    return dev <= Q_UNIT2_TOL && (qy > 0 || (qy == 0 && qx > 0));
+}
+
 constexpr int RG_MAX = 16;   // Gaussian radius ceil(4 sigma) limit (sigma <= 4)
 constexpr int K_MAX = 24;    // smoothing window half-width limit
 constexpr int R_LIMIT = 126; // r_max limit: keeps u16 vote counts and u64 scores exact
@@ -100,6 +114,9 @@ struct FitArgs {
     int32_t nstats;
 };
 
+// flags of a caller-given ridge list (BinArgs::flags)
+enum { BIN_OVERFLOW = 1, BIN_OFF_FRAME = 2, BIN_BAD_CODE = 4, BIN_DUPLICATE = 8 };
+
 struct BinArgs {
     const int32_t* xy;
     const int16_t* q;
@@ -109,7 +126,8 @@ struct BinArgs {
     uint32_t* rq;
     float* rk;
     uint32_t* bin_count;
-    uint32_t* overflow;
+    uint32_t* pixel_mask;   // 8 words (one bit per pixel) per 16 x 16 bin, zero before the launch
+    uint32_t* flags;
 };
 
 // Launchers (return hipSuccess or the launch error).

@@ -21,6 +21,7 @@
 // prediction.  Track state lives in device memory between calls.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -100,9 +101,26 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
     if (tid == 0) s_err = A.state[S_ERR];
     const float g2 = A.gate * A.gate;
     const float inv_cs = 1.0f / fmaxf(1.125f * A.gate, 0.25f);
+    auto depth = [&](float r) {
+        double disc = A.c1 * A.c1 - 4.0 * A.c2 * (A.c0 - (double)r);
+        disc = disc < 0.0 ? 0.0 : disc;          // a NaN radius stays NaN
+        return (float)((-A.c1 + sqrt(disc)) / (2.0 * A.c2));
+    };
+    __syncthreads();
 
     for (int f = 0; f < A.nframes; ++f) {
         const int d0 = A.offsets[f], n = A.offsets[f + 1] - d0;   // n <= MAX_DET, checked on the host
+        // After an overflow the track state is incomplete: no frame is linked until a reset,
+        // every id is -1 (s_err is read by all threads between the barriers that end a frame
+        // and the first barrier of this one, and written only after that barrier).
+        if (s_err != 0) {
+            for (int j = tid; j < n; j += THREADS) {
+                A.ids[d0 + j] = -1;
+                if (A.z) A.z[d0 + j] = depth(A.det[3 * (int64_t)(d0 + j) + 2]);
+            }
+            t += 1;
+            continue;
+        }
         const int32_t* act_in = cur ? A.act1 : A.act0;
         int32_t* act_out = cur ? A.act0 : A.act1;
         for (int j = tid; j < n; j += THREADS) {
@@ -257,20 +275,19 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
                     A.t_last[id] = t;
                 }
                 A.ids[d0 + j] = id;
-                if (A.z) {
-                    double disc = A.c1 * A.c1 - 4.0 * A.c2 * (A.c0 - (double)d.z);
-                    disc = disc < 0.0 ? 0.0 : disc;          // a NaN radius stays NaN
-                    A.z[d0 + j] = (float)((-A.c1 + sqrt(disc)) / (2.0 * A.c2));
-                }
+                if (A.z) A.z[d0 + j] = depth(d.z);
             }
             __syncthreads();
             if (tid == 0) for (int w = 0; w < THREADS / 64; ++w) s_base += s_wave[w];
             __syncthreads();   // s_wave is rewritten by the next step
         }
         __syncthreads();
-        const int nnew = s_base;
-        ntracks = min(ntracks + nnew, A.max_tracks);
-        nact = min(keep + nnew, MAX_ACTIVE);
+        // Fresh detections take ids ntracks + rank and slots keep + rank in detection order, so
+        // the ones that got both are exactly the first min(nnew, max_tracks - ntracks,
+        // MAX_ACTIVE - keep); only those become tracks and active slots.
+        const int made = min(s_base, min(A.max_tracks - ntracks, MAX_ACTIVE - keep));
+        ntracks += made;
+        nact = keep + made;
         t += 1;
         cur ^= 1;
         __syncthreads();   // act_out, positions and LDS reuse ordered before the next frame
@@ -308,8 +325,8 @@ static void linker_free(rd_linker_s* L) {
 
 static bool link_params_ok(const rd_link_params* p) {
     return p && p->gate > 0.f && p->gate < 1e18f && p->memory >= 0 && p->memory < (1 << 20) &&
-           p->depth_c2 != 0.0 && p->depth_c2 == p->depth_c2 && p->depth_c1 == p->depth_c1 &&
-           p->depth_c0 == p->depth_c0;
+           std::isfinite(p->depth_c0) && std::isfinite(p->depth_c1) && std::isfinite(p->depth_c2) &&
+           p->depth_c2 > 0.0;
 }
 
 extern "C" rd_status rd_linker_create(const rd_link_params* params, int32_t max_tracks,

@@ -711,24 +711,37 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     }
 }
 
-// Scatter a caller-given ridge list into the per-bin slots.
+// Scatter a caller-given ridge list into the per-bin slots, checking what keeps the votes
+// exact: pixels inside the frame, each listed once (one bit per pixel of its bin, taken by an
+// atomic), with a direction code as step 1 makes them.  Any failure sets a flag and the host
+// reports RD_E_INVALID.
 __global__ __launch_bounds__(NT) void k_bin(BinArgs a) {
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * NT) {
         const int x = a.xy[2 * i], y = a.xy[2 * i + 1];
+        const int qx = a.q[2 * i], qy = a.q[2 * i + 1];
         if (x < 0 || x >= a.W || y < 0 || y >= a.H) {
-            atomicOr(a.overflow, 2u);
+            atomicOr(a.flags, static_cast<uint32_t>(BIN_OFF_FRAME));
+            continue;
+        }
+        if (!ridge_code_ok(qx, qy)) {
+            atomicOr(a.flags, static_cast<uint32_t>(BIN_BAD_CODE));
             continue;
         }
         const int64_t bin = (int64_t)(y >> BIN_SHIFT) * a.nbx + (x >> BIN_SHIFT);
-        const uint32_t pos = atomicAdd(&a.bin_count[bin], 1u);
+        const int lp = ((y & (BIN - 1)) << BIN_SHIFT) | (x & (BIN - 1));
+        const uint32_t bit = 1u << (lp & 31);
+        if (atomicOr(&a.pixel_mask[bin * 8 + (lp >> 5)], bit) & bit) {
+            atomicOr(a.flags, static_cast<uint32_t>(BIN_DUPLICATE));
+            continue;
+        }
+        const uint32_t pos = atomicAdd(&a.bin_count[bin], 1u);   // < BIN_CAP: distinct pixels of one bin
         if (pos >= static_cast<uint32_t>(BIN_CAP)) {
-            atomicOr(a.overflow, 1u);
+            atomicOr(a.flags, static_cast<uint32_t>(BIN_OVERFLOW));
             continue;
         }
         const int64_t slot = bin * BIN_CAP + pos;
         a.rxy[slot] = static_cast<uint32_t>(x) | (static_cast<uint32_t>(y) << 16);
-        a.rq[slot] = (static_cast<uint32_t>(static_cast<uint16_t>(a.q[2 * i]))) |
-                     (static_cast<uint32_t>(static_cast<uint16_t>(a.q[2 * i + 1])) << 16);
+        a.rq[slot] = (static_cast<uint32_t>(static_cast<uint16_t>(qx))) | (static_cast<uint32_t>(static_cast<uint16_t>(qy)) << 16);
         a.rk[slot] = 0.0f;
     }
 }

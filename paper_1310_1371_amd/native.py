@@ -64,6 +64,7 @@ SIGNATURES = {
     "rd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rd_validate_params": (ctypes.c_int, [_P(RdParams)]),
     "rd_level_tables": (ctypes.c_int, [_P(RdParams), _i32, _vp, _vp, _vp]),
+    "rd_validate_ridges": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32]),
     "rd_create": (ctypes.c_int, [_P(RdCreateInfo), _P(_vp)]),
     "rd_destroy": (None, [_vp]),
     "rd_detect": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _P(RdRing), _i32, _P(_i32)]),

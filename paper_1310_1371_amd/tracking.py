@@ -46,15 +46,23 @@ class Linker:
     def reset(self):
         N.check(self._lib.rd_linker_reset(self._h), "rd_linker_reset")
 
+    def _info_raw(self):
+        """(tracks, active, frame) without raising on a recorded overflow."""
+        nt, na, fr = N._i32(), N._i32(), N._i32()
+        self._lib.rd_linker_info(self._h, ctypes.byref(nt), ctypes.byref(na), ctypes.byref(fr))
+        return nt.value, na.value, fr.value
+
     def info(self) -> dict:
         nt, na, fr = N._i32(), N._i32(), N._i32()
         st = self._lib.rd_linker_info(self._h, ctypes.byref(nt), ctypes.byref(na), ctypes.byref(fr))
         N.check(st, "rd_linker_info")
         return {"tracks": nt.value, "active": na.value, "frame": fr.value}
 
-    def link(self, det: torch.Tensor, offsets, want_depth: bool = True):
+    def link(self, det: torch.Tensor, offsets, want_depth: bool = True, strict: bool = True):
         """det: float32 (n, 3) device tensor, frames back to back; offsets: nframes + 1 prefix
-        offsets (host).  Returns (ids int32, z float32 or None), device tensors of length n."""
+        offsets (host).  Returns (ids int32, z float32 or None), device tensors of length n.
+        With strict=False an overflow does not raise: the call returns (ids, z, status), ids
+        being -1 where no track could be given."""
         offs = np.ascontiguousarray(offsets, dtype=np.int32)
         nframes = len(offs) - 1
         det = det.contiguous()
@@ -69,5 +77,7 @@ class Linker:
                                    offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nframes,
                                    ctypes.c_void_p(ids.data_ptr()),
                                    ctypes.c_void_p(z.data_ptr()) if z is not None else None)
+        if not strict and st == N.RD_E_OVERFLOW:
+            return ids, z, st
         N.check(st, "rd_link")
-        return ids, z
+        return (ids, z) if strict else (ids, z, st)

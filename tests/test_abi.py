@@ -102,7 +102,8 @@ def test_create_without_gpu_reports_device_error():
 
 @pytest.mark.parametrize("gate,memory,c2,max_tracks", [
     (0.0, 1, 72.0, 100), (-1.0, 1, 72.0, 100), (float("nan"), 1, 72.0, 100), (5.0, -1, 72.0, 100),
-    (5.0, 1, 0.0, 100), (5.0, 1, float("nan"), 100), (5.0, 1, 72.0, 0)])
+    (5.0, 1, 0.0, 100), (5.0, 1, float("nan"), 100), (5.0, 1, 72.0, 0),
+    (5.0, 1, -72.0, 100), (5.0, 1, float("inf"), 100)])
 def test_linker_parameters_are_validated_before_device_work(gate, memory, c2, max_tracks):
     lib = _ensure_built()
     h = ctypes.c_void_p()

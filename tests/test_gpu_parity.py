@@ -191,8 +191,7 @@ def test_dense_ridges_pieces_and_per_level_hotspots(det):
     yy, xx = np.mgrid[20:140, 20:140]
     xs, ys = xx.ravel().astype(np.int64), yy.ravel().astype(np.int64)
     th = np.random.default_rng(7).uniform(0.0, 2.0 * np.pi, xs.size)
-    qx = np.rint(16384 * np.cos(th)).astype(np.int64)
-    qy = np.rint(16384 * np.sin(th)).astype(np.int64)
+    qx, qy = O.direction_code(np.cos(th), np.sin(th))
     p = dict(O.DEFAULTS, **dict(synth.PARAMS_C1, vote_threshold=0, peak_fraction=50.0))
     _, A_ref, S_ref = O.detect_from_ridges(xs, ys, qx, qy, W, H, p, return_volumes=True)
     xy = np.stack([xs, ys], 1).astype(np.int32)
@@ -211,7 +210,7 @@ def test_strong_list_overflow_is_reported(det):
     xs, ys = xx.ravel(), yy.ravel()
     th = np.random.default_rng(7).uniform(0.0, 2.0 * np.pi, xs.size)
     xy = np.stack([xs, ys], 1).astype(np.int32)
-    q = np.stack([np.rint(16384 * np.cos(th)), np.rint(16384 * np.sin(th))], 1).astype(np.int16)
+    q = np.stack(O.direction_code(np.cos(th), np.sin(th)), 1).astype(np.int16)
     p = dict(O.DEFAULTS, **dict(synth.PARAMS_C1, vote_threshold=0, peak_fraction=0.0))
     with pytest.raises(N.RdError) as e:
         det.accumulate(xy, q, 160, 160, p)
@@ -515,3 +514,41 @@ def test_invalid_arguments_rejected_before_launch(det):
     with pytest.raises(N.RdError) as e:
         det.detect_from_ridges(xy, q, 256, 256, f.params)
     assert e.value.status == N.RD_E_INVALID
+
+
+@pytest.mark.parametrize("case", ["duplicate", "non_unit", "negative_sign", "zero", "bin_of_257"])
+def test_ridge_lists_outside_the_exact_class_are_rejected(det, case):
+    """Lists that could break the exactness of the integer votes (a pixel twice, a code that
+    is not a unit direction in canonical sign) are refused by both stage entry points, on
+    the device, with RD_E_INVALID; the host check agrees."""
+    from paper_1310_1371_amd import native as N
+    say(f"[ridges] invalid caller list: {case}")
+    f = synth.config1()
+    xs, ys, qx, qy, xy, q = _oracle_ridge_inputs(f)
+    xy, q = xy.copy(), q.copy()
+    if case == "duplicate":
+        xy = np.concatenate([xy, xy[5:6]])
+        q = np.concatenate([q, q[5:6]])
+    elif case == "non_unit":
+        q[7] = (16384, 200)                  # |q|^2 - 2^28 = 40000 > 2^15
+    elif case == "negative_sign":
+        q[3] = (-q[3, 0], -q[3, 1]) if q[3, 1] != 0 else (-q[3, 0], 0)
+    elif case == "zero":
+        q[2] = (0, 0)
+    else:                                     # 257 entries in one 16 x 16 bin
+        yy, xx = np.mgrid[0:16, 0:16]
+        xy = np.concatenate([np.stack([xx.ravel() + 32, yy.ravel() + 32], 1), [[40, 40]]]).astype(np.int32)
+        q = np.tile(np.array([[0, 16384]], np.int16), (257, 1))
+    assert N.lib().rd_validate_ridges(np.ascontiguousarray(xy, np.int32).ctypes.data,
+                                      np.ascontiguousarray(q, np.int16).ctypes.data, len(xy), 256, 256) \
+        == N.RD_E_INVALID
+    for call in (lambda: det.accumulate(xy, q, 256, 256, f.params, scores=False),
+                 lambda: det.detect_from_ridges(xy, q, 256, 256, f.params)):
+        with pytest.raises(N.RdError) as e:
+            call()
+        assert e.value.status == N.RD_E_INVALID
+    # the list of step 2 itself passes, and still gives the oracle's rings
+    xs, ys, qx, qy, xy, q = _oracle_ridge_inputs(f)
+    assert N.lib().rd_validate_ridges(xy.ctypes.data, q.ctypes.data, len(xy), 256, 256) == N.RD_OK
+    got = det.detect_from_ridges(xy, q, 256, 256, f.params)
+    assert len(got) == len(O.detect_from_ridges(xs, ys, qx, qy, 256, 256, dict(O.DEFAULTS, **f.params)))

@@ -167,3 +167,53 @@ def test_capacity_errors(linker_cls):
     lk.reset()
     _check(lk, T.Tracker(5.0, 0), [frames[0][:90]])
     lk.close()
+
+
+def test_track_overflow_leaves_no_stale_track(linker_cls):
+    """Too many tracks: the first max_tracks fresh detections (in detection order) open
+    tracks, the rest get -1, and every later frame, in the same call and the next one, gets
+    -1 throughout; the linker reports exactly max_tracks tracks until a reset."""
+    from paper_1310_1371_amd.native import RD_E_OVERFLOW
+    say("[track] overflow of the track store: ids after the overflow")
+    lk = linker_cls(5.0, 1, max_tracks=100)
+    frames = _walk_frames(9, 150, 4, spurious=0)
+    det, offs = _pack(frames[:3])
+    ids, z, st = lk.link(det, offs, strict=False)
+    assert st == RD_E_OVERFLOW
+    got = ids.cpu().numpy()
+    n0 = int(offs[1])
+    assert got[:100].tolist() == list(range(100))
+    assert (got[100:n0] == -1).all() and (got[n0:] == -1).all()
+    zr = T.depth(det.cpu().numpy()[:, 2].astype(np.float64), 8.0, 0.0, 72.0).astype(f32)
+    assert np.array_equal(z.cpu().numpy(), zr, equal_nan=True)
+    det2, offs2 = _pack(frames[3:])
+    ids2, _, st2 = lk.link(det2, offs2, strict=False)
+    assert st2 == RD_E_OVERFLOW and (ids2.cpu().numpy() == -1).all()
+    nt, na, fr = lk._info_raw()
+    assert nt == 100 and na <= 100 and fr == 4
+    lk.reset()
+    _check(lk, T.Tracker(5.0, 1), [frames[0][:90]])
+    lk.close()
+
+
+def test_active_overflow_leaves_no_stale_slot(linker_cls):
+    """Too many tracks taking part in one frame: two frames of 4096 detections that match
+    nothing (frame 1 far from frame 0) keep 4096 tracks and open 6144 - 4096 = 2048 more; the
+    other fresh detections of frame 1 get -1, and frame 2 is not linked."""
+    from paper_1310_1371_amd.native import RD_E_OVERFLOW
+    say("[track] overflow of the active list: ids after the overflow")
+    lk = linker_cls(2.0, 3, max_tracks=1 << 16)
+    rng = np.random.default_rng(4)
+    fr = [np.stack([rng.uniform(0, 1000, 4096), rng.uniform(0, 1000, 4096), np.full(4096, 20.0)], 1),
+          np.stack([rng.uniform(5000, 6000, 4096), rng.uniform(0, 1000, 4096), np.full(4096, 20.0)], 1),
+          np.stack([rng.uniform(0, 1000, 16), rng.uniform(0, 1000, 16), np.full(16, 20.0)], 1)]
+    det, offs = _pack([f.astype(f32) for f in fr])
+    ids, _, st = lk.link(det, offs, strict=False)
+    assert st == RD_E_OVERFLOW
+    got = ids.cpu().numpy()
+    assert got[:4096].tolist() == list(range(4096))
+    assert got[4096:4096 + 2048].tolist() == list(range(4096, 6144))
+    assert (got[4096 + 2048:] == -1).all()
+    nt, na, frame = lk._info_raw()
+    assert nt == 6144 and na == 6144 and frame == 3
+    lk.close()
