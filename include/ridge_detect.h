@@ -241,6 +241,32 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
                            int64_t n, int32_t width, int32_t height, const rd_params* params,
                            rd_ring* out, int32_t capacity, int32_t* n_rings);
 
+/* ---- detection without allocation ------------------------------------------------------
+ *
+ * For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc and friends): rd_detect on one device-resident frame with no context.  Every
+ * buffer the pipeline passes between its kernels (ridge bins, peak list, counters, level
+ * tables, frame descriptor, ring staging) lives in one static device array of
+ * RD_NOALLOC_SCRATCH_BYTES on each GPU the call runs on, held until the process ends; the
+ * call itself allocates nothing (no hipMalloc, no hipFree, no allocating library routine).
+ * The kernels and the tuning are rd_detect's defaults, so the ring list is bit-identical to
+ * rd_detect's on the same frame and parameters.
+ *   - frame->on_device must be 1, width and height <= RD_NOALLOC_MAX_DIM (RD_E_TOO_LARGE
+ *     beyond; the other frame rules as rd_detect).
+ *   - The work runs on the calling thread's current device, ordered on `stream` (a
+ *     hipStream_t; NULL = the default stream), and has completed when the call returns.
+ *   - out_dev: a device array of `capacity` rings, written in ascending (r_bin, b, a) order;
+ *     *n_rings (host) receives the count.  RD_E_TRUNCATED as rd_detect; RD_E_OVERFLOW when a
+ *     frame has more than RD_NOALLOC_MAX_PEAKS peaks (or a vote tile's list overflowed).
+ *   - All calls on one GPU share its array, which keeps the last call's contents: calls that
+ *     overlap on one GPU (other threads, other streams) race and must be serialised by the
+ *     caller. */
+#define RD_NOALLOC_MAX_DIM 1024
+#define RD_NOALLOC_MAX_PEAKS 8192
+#define RD_NOALLOC_SCRATCH_BYTES (13 * 1024 * 1024)
+rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* params, void* stream,
+                            rd_ring* out_dev, int32_t capacity, int32_t* n_rings);
+
 /* ---- differentiable extension ------------------------------------------------------------
  *
  * The paper's votes are integer and its ridge selection is a threshold, so nothing of

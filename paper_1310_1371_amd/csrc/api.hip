@@ -18,7 +18,6 @@ namespace {
 constexpr double TWO_PI = 6.283185307179586;
 constexpr double S_SCALE = 1073741824.0;   // 2^30
 constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per level chunk
-constexpr int FIT_BLOCKS = 512;
 constexpr int NSTATS = 8 + 64;             // u64: votes, hotspots, strong, taps, -, -, -, -, 64 ridge stripes
 
 double level_sigma(const rd_params& p, int r) {
@@ -28,11 +27,25 @@ double level_sigma(const rd_params& p, int r) {
 int level_radius(const rd_params& p, int r) { return static_cast<int>(std::ceil(3.0 * level_sigma(p, r))); }
 
 void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
+    FixedTables f;
+    build_fixed_tables(p, f, budget);
+    t.lbase = f.lbase;
+    t.L = f.L;
+    t.wtab.assign(f.wtab, f.wtab + static_cast<size_t>(f.L) * (K_MAX + 1));
+    t.ktab.assign(f.ktab, f.ktab + f.L);
+    t.thr.assign(f.thr, f.thr + f.L);
+    t.chunks.assign(f.chunks, f.chunks + f.nchunks + 1);
+    t.lds = f.lds;
+}
+
+}  // namespace
+
+namespace rd {
+
+void build_fixed_tables(const rd_params& p, FixedTables& t, size_t budget) {
     t.lbase = p.r_min - 1;
     t.L = p.r_max - p.r_min + 3;
-    t.wtab.assign(static_cast<size_t>(t.L) * (K_MAX + 1), 0u);
-    t.ktab.assign(t.L, 0);
-    t.thr.assign(t.L, 0ull);
+    std::memset(t.wtab, 0, sizeof(t.wtab));
     for (int i = 0; i < t.L; ++i) {
         const int l = t.lbase + i;
         const double sg = level_sigma(p, l);
@@ -45,7 +58,7 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
             std::floor(static_cast<double>(p.peak_fraction) * TWO_PI * static_cast<double>(l) * S_SCALE));
     }
     // greedy level chunks: peak levels [rc0, rc1) need accumulator levels rc0-1 .. rc1
-    t.chunks.clear();
+    t.nchunks = 0;
     t.lds = 0;
     int rc0 = p.r_min;
     while (rc0 <= p.r_max) {
@@ -53,16 +66,31 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
         while (rc1 <= p.r_max && rc1 + 1 - rc0 <= CHUNK_MAX &&
                vote_lds_bytes(VOTE_TILE, rc1 + 1 - rc0 + 2, t.ktab[rc1 + 1 - t.lbase]) <= budget)
             ++rc1;
-        t.chunks.push_back(rc0);
+        t.chunks[t.nchunks++] = rc0;
         t.lds = std::max(t.lds, vote_lds_bytes(VOTE_TILE, rc1 - rc0 + 2, t.ktab[rc1 - t.lbase]));
         rc0 = rc1;
     }
-    t.chunks.push_back(p.r_max + 1);
+    t.chunks[t.nchunks] = p.r_max + 1;
 }
 
-}  // namespace
-
-namespace rd {
+StencilArgs stencil_args_for(const rd_params& p, const FrameDesc* frames, int nframes, int total_tiles) {
+    StencilArgs a{};
+    a.frames = frames;
+    a.nframes = nframes;
+    a.total_tiles = total_tiles;
+    const double sg = p.sigma_smooth;
+    const int R = gauss_radius(p.sigma_smooth);
+    double sum = 0.0;
+    double g[RG_MAX + 1] = {0};
+    for (int i = 0; i <= R; ++i) {
+        g[i] = std::exp(-(double)(i * i) / (2.0 * sg * sg));
+        sum += (i == 0 ? 1.0 : 2.0) * g[i];
+    }
+    for (int i = 0; i <= RG_MAX; ++i) a.g[i] = i <= R ? g[i] / sum : 0.0;
+    a.k_threshold = p.k_threshold;
+    a.edge = p.measure == RD_MEASURE_EDGE ? 1 : 0;
+    return a;
+}
 
 int gauss_radius(float sigma) { return static_cast<int>(std::ceil(4.0 * static_cast<double>(sigma))); }
 
@@ -126,21 +154,7 @@ rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int var
 }
 
 StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_tiles) {
-    StencilArgs a{};
-    a.frames = h->d_frames;
-    a.nframes = nframes;
-    a.total_tiles = total_tiles;
-    const double sg = p.sigma_smooth;
-    const int R = gauss_radius(p.sigma_smooth);
-    double sum = 0.0;
-    double g[RG_MAX + 1] = {0};
-    for (int i = 0; i <= R; ++i) {
-        g[i] = std::exp(-(double)(i * i) / (2.0 * sg * sg));
-        sum += (i == 0 ? 1.0 : 2.0) * g[i];
-    }
-    for (int i = 0; i <= RG_MAX; ++i) a.g[i] = i <= R ? g[i] / sum : 0.0;
-    a.k_threshold = p.k_threshold;
-    a.edge = p.measure == RD_MEASURE_EDGE ? 1 : 0;
+    StencilArgs a = stencil_args_for(p, h->d_frames, nframes, total_tiles);
     a.rxy = h->d_rxy;
     a.rq = h->d_rq;
     a.rk = h->d_rk;
@@ -288,7 +302,7 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
     RD_TRY(mark(h, 1));
     RD_HIP(launch_vote(vote_args(h, p, nframes, tv), h->tabs.lds, false, h->cus, h->stream));
     RD_TRY(mark(h, 2));
-    RD_HIP(launch_fit(fit_args(h, p, nframes, rings, counts_out), FIT_BLOCKS, h->stream));
+    RD_HIP(launch_fit(fit_args(h, p, nframes, rings, counts_out), FIT_GRID, h->stream));
     RD_TRY(mark(h, 3));
     return RD_OK;
 }

@@ -31,6 +31,23 @@ struct LevelTables {
     size_t lds = 0;
 };
 
+// The same tables in fixed-size arrays (no heap), for the entry point that allocates nothing.
+struct FixedTables {
+    int lbase = 0, L = 0, nchunks = 0;
+    uint32_t wtab[(R_LIMIT + 3) * (K_MAX + 1)];
+    int32_t ktab[R_LIMIT + 3];
+    uint64_t thr[R_LIMIT + 3];
+    int32_t chunks[R_LIMIT + 4];
+    size_t lds = 0;
+};
+
+// Level tables of *p for a vote-histogram LDS budget of `budget` bytes.
+void build_fixed_tables(const rd_params& p, FixedTables& t, size_t budget);
+
+// Ridge-kernel arguments that depend on the parameters only (smoothing taps, threshold,
+// measure); the caller fills in the output pointers.
+StencilArgs stencil_args_for(const rd_params& p, const FrameDesc* frames, int nframes, int total_tiles);
+
 inline bool same_params(const rd_params& a, const rd_params& b) {
     return std::memcmp(&a, &b, sizeof(rd_params)) == 0;
 }

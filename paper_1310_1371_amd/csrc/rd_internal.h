@@ -145,6 +145,7 @@ hipError_t vote_prepare();   // one-time kernel attributes (outside any graph ca
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s);
 hipError_t launch_zero(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_zero2(uint32_t* p, int n, uint32_t* p2, int n2, hipStream_t s);   // both ranges, one launch
+constexpr int FIT_GRID = 512;   // workgroups of the fit kernel (each takes peaks in turn)
 hipError_t launch_fit(const FitArgs& a, int blocks, hipStream_t s);
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* rk, const uint32_t* bin_count,
