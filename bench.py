@@ -16,13 +16,16 @@ Also reported, on the same GPU:
   - differentiable: 16 float32 1024^2 frames with 300 rings each: detection, soft
     accumulator + ring-profile loss forward and backward, 20 Levenberg-Marquardt steps per
     detected ring, and the accuracy of refined vs algebraic-fit rings against the truth;
-  - stream: a slice of the 2048^2 uint16 sequence with 1000 moving rings, 32 frames per
-    launch, host-to-device copies overlapped on a second stream, refinement of all
-    detections, linking of the refined rings into tracks with depths, link accuracy against
-    the generator's truth;
+  - stream: the whole 2000-frame 2048^2 uint16 sequence with 1000 moving rings (rendered on
+    the GPU before the timed region and resident in HBM), 32 frames per launch, refinement of
+    all detections, linking of the refined rings into tracks with depths, link accuracy
+    against the generator's truth over the whole sequence;
   - edges: the plain step with directed edges (gradient magnitude) on the headline frame;
-  - the dominant kernel's roofline figures;
-  - the CPU oracle timed on a bounded sample of the headline workload.
+  - the dominant kernel's roofline figures, against the LDS datapath and against the LDS
+    atomic rate measured on the same GPU;
+  - the CPU oracle timed on a bounded sample of the headline workload (one process, and a
+    pool of processes over frames, the paper's scaling model), and its agreement with the
+    GPU on the headline frame.
 
 Prints one JSON line.
 """
@@ -31,6 +34,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import multiprocessing
 import os
 import re
 import sys
@@ -41,8 +45,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # The fused vote / smoothing / peak kernel runs out of LDS (the accumulator never reaches HBM):
-# its ceiling is the LDS datapath, 256 CUs x 32 banks x 4 bytes per clock at 2.4 GHz
+# its ceiling is the LDS datapath, 256 CUs x 32 banks x 4 bytes per clock at 2.4 GHz (GB/s)
 LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
+POOL_MAX = 16        # worker processes at most (the host share of one GPU)
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "vote_c2_1024_traffic.md")
 
 
@@ -57,12 +62,30 @@ def parse():
     ap.add_argument("--edge-steps", type=int, default=100, help="plain steps with directed edges (0: skip)")
     ap.add_argument("--diff-frames", type=int, default=16, help="frames of the differentiable step (0: skip)")
     ap.add_argument("--diff-steps", type=int, default=3)
-    ap.add_argument("--stream-launches", type=int, default=3, help="32-frame launches of the stream (0: skip)")
-    ap.add_argument("--cpu-frames", type=int, default=12, help="frames of the CPU-oracle sample")
+    ap.add_argument("--stream-frames", type=int, default=2000, help="frames of the stream, 32 per launch (0: skip)")
+    ap.add_argument("--cpu-frames", type=int, default=8, help="frames of the single-process oracle sample")
+    ap.add_argument("--cpu-pool-frames", type=int, default=32, help="frames of the frame-parallel oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-sized device buffer 10 times (reference for HBM byte counters)")
+    ap.add_argument("--lds-calibration", action="store_true",
+                    help="only measure the LDS atomic-add rate (the vote step's ceiling)")
     return ap.parse_args()
+
+
+def lds_ceiling():
+    """LDS atomic adds per second at random addresses, with and without the returned value,
+    measured by the library's calibration kernel on device 0."""
+    import ctypes
+
+    from paper_1310_1371_amd import native as N
+    out = {}
+    for rtn, name in ((1, "with_return"), (0, "no_return")):
+        rate, ms = ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().rd_measure_lds_atomics(0, rtn, ctypes.byref(rate), ctypes.byref(ms)),
+                "rd_measure_lds_atomics")
+        out[name] = {"atomics_per_s": rate.value, "launch_ms": ms.value}
+    return out
 
 
 def copy_calibration(nbytes: int):
@@ -81,29 +104,110 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def pool_size():
+    return max(1, min(POOL_MAX, len(os.sched_getaffinity(0))))
+
+
 def pool_map(fn, items):
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+    """fn over items in worker processes started fresh (spawn): this process may hold a GPU
+    context, which a forked child must not inherit."""
+    with ProcessPoolExecutor(max_workers=pool_size(), mp_context=multiprocessing.get_context("spawn")) as ex:
         return list(ex.map(fn, items))
 
 
-def cpu_baseline(n_frames: int):
-    """The FP64 oracle on a bounded sample of the headline workload, one host thread."""
+def _oracle_timed(args):
+    """Worker: the oracle on one frame in one thread; (seconds, rings)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import ridge_hough as O
-    from paper_1310_1371_amd import synth
-
-    frames = [synth.config2(seed=1000 + i) for i in range(n_frames)]
+    img, params = args
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        for f in frames:
-            O.detect(f.image, f.params)
-        dt = time.perf_counter() - t0
-    px = sum(f.image.size for f in frames)
-    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-            "frames_per_s": n_frames / dt,
-            "sample": f"{n_frames} frames of 1024x1024 u16 with 200 rings (seeds 1000..{999 + n_frames}), "
-                      f"{dt:.1f} s on one host thread"}
+        rings = O.detect(img, params)
+        return time.perf_counter() - t0, rings
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, headline, batch_frames, uneven_frames):
+    """The FP64 oracle on bounded samples of the workloads: one process (one thread) on
+    `args.cpu_frames` headline-kind frames, the headline frame first, and a pool of processes
+    over frames (the paper's scaling model: one process per core) on the c2 batch and on part
+    of the uneven batch.  Returns (cpu_baseline, the oracle's rings of the headline frame)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ridge_hough as O
+
+    single = [headline] + batch_frames[:max(args.cpu_frames - 1, 0)]
+    head_rings = None
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for i, f in enumerate(single):
+            r = O.detect(f.image, f.params)
+            if i == 0:
+                head_rings = r
+        dt1 = time.perf_counter() - t0
+    px1 = sum(f.image.size for f in single)
+    P = pool_size()
+    legs = {}
+    with ProcessPoolExecutor(max_workers=P, mp_context=multiprocessing.get_context("spawn")) as ex:
+        list(ex.map(_oracle_timed, [(f.image[:32, :32].copy(), f.params) for f in batch_frames[:P]]))   # start-up
+        for name, frames in (("c2_batch", batch_frames[:args.cpu_pool_frames]),
+                             ("uneven_batch", uneven_frames[:max(args.cpu_pool_frames // 2, 1)])):
+            if not frames:
+                continue
+            t0 = time.perf_counter()
+            res = list(ex.map(_oracle_timed, [(f.image, f.params) for f in frames]))
+            dt = time.perf_counter() - t0
+            px = sum(f.image.size for f in frames)
+            legs[name] = {"value": px / dt / 1e6, "unit": "Mpixel/s", "frames_per_s": len(frames) / dt,
+                          "frames": len(frames), "wall_s": dt, "cpu_s": sum(r[0] for r in res)}
+    main = legs.get("c2_batch")
+    out = {"value": main["value"] if main else px1 / dt1 / 1e6, "unit": "Mpixel/s", "cores": P if main else 1,
+           "kind": "oracle", "cpu_model": _cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
+           "frames_per_s": main["frames_per_s"] if main else len(single) / dt1,
+           "sample": (f"{main['frames']} frames of 1024x1024 u16 with 200 rings (seeds 1000..) over a pool of "
+                      f"{P} single-thread processes, {main['wall_s']:.1f} s wall, {main['cpu_s']:.1f} s of CPU"
+                      if main else f"{len(single)} frames on one thread"),
+           "frame_parallel": legs,
+           "single_process": {"value": px1 / dt1 / 1e6, "unit": "Mpixel/s", "cores": 1,
+                              "frames_per_s": len(single) / dt1, "frames": len(single), "wall_s": dt1,
+                              "sample": f"the headline frame and {len(single) - 1} more of its kind, one thread"}}
+    return out, head_rings
+
+
+def parity_block(det, headline, head_rings, frame_dev):
+    """The GPU against the oracle on the headline frame: ridge sets (symmetric difference over
+    the oracle's ridge count) and ring lists (matched by Hough voxel; unmatched both ways; the
+    largest centre / radius difference of the matched rings)."""
+    import numpy as np
+
+    from oracle import ridge_hough as O
+    p = headline.params
+    xs, ys, _, _, _ = O.ridges(headline.image, p)
+    xy, _, _ = det.ridges(frame_dev, p)
+    so = set(zip(xs.tolist(), ys.tolist()))
+    sg = set(map(tuple, xy.cpu().numpy().tolist()))
+    gpu = det.detect(frame_dev, p)
+    kr = {(int(r["a"]), int(r["b"]), int(r["r_bin"])): r for r in head_rings}
+    kg = {(int(r["a"]), int(r["b"]), int(r["r_bin"])): r for r in gpu}
+    common = set(kr) & set(kg)
+    dmax = max((max(abs(float(kr[k][f]) - float(kg[k][f])) for f in ("cx", "cy", "r")) for k in common),
+               default=0.0)
+    return {"frame": "the headline frame (1024x1024 u16, seed 1)",
+            "ridges_oracle": len(so), "ridges_gpu": len(sg), "ridge_symmetric_difference": len(so ^ sg),
+            "ridge_mismatch_pct": 100.0 * len(so ^ sg) / max(len(so), 1),
+            "rings_oracle": len(kr), "rings_gpu": len(kg), "rings_matched": len(common),
+            "unmatched_oracle_rings": len(set(kr) - set(kg)), "unmatched_gpu_rings": len(set(kg) - set(kr)),
+            "max_abs_diff_px": dmax, "tolerance_px": 0.05}
 
 
 def traffic_from_profile(kernel_src: str):
@@ -137,19 +241,30 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.lds_calibration:
+        print(json.dumps({"lds_atomic_rate": lds_ceiling()}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: frames are independent, so a batch would shard by frames "
               "across GPUs with no collective; multi-GPU runs are not part of this build.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     from paper_1310_1371_amd import synth
+
+    # host frames first (worker processes are spawned, never forked from a GPU process)
+    log("[bench] host frames")
+    f = synth.config2()
+    batch_host = pool_map(synth.config2, [1000 + i for i in range(max(args.batch, args.cpu_pool_frames,
+                                                                      args.cpu_frames))])
+    uneven_host = pool_map(synth.config3_frame, synth.config3_plan(2, args.uneven)) if args.uneven > 0 else []
+
+    import torch
+
     from paper_1310_1371_amd.detector import Detector
 
     log("[bench] headline frame")
-    f = synth.config2()
     H, W = f.image.shape
     p = f.params
     frame = torch.from_numpy(f.image).cuda()
@@ -187,26 +302,29 @@ def main():
     torch.cuda.synchronize()
     dt_graph = time.perf_counter() - t0
 
-    # ---- roofline of the dominant kernel (the vote / smoothing / peak kernel).  Algorithmic
-    # LDS bytes per launch: every cell of the W x H x L accumulator is cleared and tested against
-    # T_int once (2 + 2 bytes of u16 counter), and every one of the 2 L N_ridge votes is one
-    # 4-byte atomic read-modify-write.  The smoothing taps at hotspots come on top and are not
-    # counted (a lower bound on the work).
+    # ---- roofline of the dominant kernel (the vote / smoothing / peak kernel).  Its algorithmic
+    # work is the 2 L N_ridge votes, one 4-byte LDS atomic add each; the accumulator's cells and
+    # the smoothing taps at hotspots are not counted.  Ceilings: the LDS datapath, and the LDS
+    # atomic-add rate at random addresses measured on this GPU by the calibration kernel.
     dom = max(kernel_ms, key=kernel_ms.get)
     L = p["r_max"] - p["r_min"] + 3
     votes = 2 * L * n_ridges
-    cells = W * H * L
-    lds_bytes = 4 * cells + 4 * votes
+    lds_bytes = 4 * votes
     launch_s = kernel_ms["vote"] * 1e-3
-    roof = {"bound": "alu", "kernel": "k_vote (votes, hotspot smoothing, 3x3x3 peaks)" if dom == "vote" else dom,
+    ceiling = lds_ceiling()
+    best_rate = max(v["atomics_per_s"] for v in ceiling.values())
+    roof = {"bound": "lds", "kernel": "k_vote (votes, hotspot smoothing, 3x3x3 peaks)" if dom == "vote" else dom,
             "achieved": lds_bytes / launch_s / 1e9,
             "peak": LDS_PEAK_GBS, "unit": "GB/s",
-            "work": f"LDS bytes: 4 x {cells} accumulator cells ({W}x{H}x{L}, cleared + tested) + 4 x {votes} "
-                    f"votes (2 x {L} levels x {n_ridges} ridges) = {lds_bytes} per launch; peak = LDS datapath, "
-                    f"256 CUs x 128 B/clock x 2.4 GHz",
+            "work": f"2 x {L} levels x {n_ridges} ridges = {votes} votes per launch, one 4-byte LDS atomic add "
+                    f"each ({lds_bytes} B); peak = LDS datapath, 256 CUs x 128 B/clock x 2.4 GHz",
             "votes_per_s": votes / launch_s,
             "launch_ms": kernel_ms["vote"],
-            "traffic": traffic_from_profile(os.path.join(ROOT, "paper_1310_1371_amd", "csrc", "vote.hip"))}
+            "traffic": traffic_from_profile(os.path.join(ROOT, "paper_1310_1371_amd", "csrc", "vote.hip")),
+            "lds_atomic_ceiling": {"atomics_per_s": best_rate, "frac": votes / launch_s / best_rate,
+                                   "measured": ceiling,
+                                   "how": "rd_measure_lds_atomics: 1024-thread workgroups, 64 KiB of counters "
+                                          "each, random 16-bit halves, best of 3 launches"}}
     roof["frac"] = roof["achieved"] / roof["peak"]
 
     out = {
@@ -237,8 +355,7 @@ def main():
     # ---- batched: 64 frames of the same workload in one launch sequence (graph replay)
     if args.batch > 0:
         log(f"[bench] batched {args.batch} frames")
-        frames = [torch.from_numpy(fr.image).cuda()
-                  for fr in pool_map(synth.config2, [1000 + i for i in range(args.batch)])]
+        frames = [torch.from_numpy(fr.image).cuda() for fr in batch_host[:args.batch]]
         for _ in range(2):
             det.detect_batch(frames, p)
         torch.cuda.synchronize()
@@ -274,13 +391,14 @@ def main():
                           "workload": f"{args.batch} frames of 1024x1024 u16, 200 rings each (seeds 1000..)"}
         del frames
 
-    # ---- uneven batch
+    # ---- uneven batch, with the launch shapes the autotuner picks for it
     if args.uneven > 0:
         log(f"[bench] uneven batch of {args.uneven}")
-        ufs = pool_map(synth.config3_frame, synth.config3_plan(2, args.uneven))
-        uframes = [torch.from_numpy(fr.image).cuda() for fr in ufs]
-        upx = sum(fr.image.size for fr in ufs)
-        pu = ufs[0].params
+        uframes = [torch.from_numpy(fr.image).cuda() for fr in uneven_host]
+        upx = sum(fr.image.size for fr in uneven_host)
+        pu = uneven_host[0].params
+        default_tuning = det.get_tuning()
+        tuned = det.autotune(uframes, pu, reps=2)
         for _ in range(2):
             det.detect_batch(uframes, pu)
         torch.cuda.synchronize()
@@ -294,32 +412,35 @@ def main():
             det.detect(fr, pu)
         torch.cuda.synchronize()
         dtp = time.perf_counter() - t0
+        det.set_tuning(**default_tuning)
         out["uneven_batch"] = {"frames": args.uneven, "mpixels": upx / 1e6, "value": upx / dtu / 1e6,
                                "unit": "Mpixel/s", "frames_per_s": args.uneven / dtu, "ms_per_batch": dtu * 1e3,
                                "plain_per_frame_frames_per_s": args.uneven / dtp,
                                "rings_found": int(sum(len(r) for r in res)),
-                               "rings_placed": int(sum(len(fr.R) for fr in ufs)),
+                               "rings_placed": int(sum(len(fr.R) for fr in uneven_host)),
+                               "autotuned": tuned, "default_tuning": default_tuning,
                                "workload": "64 u16 frames, sizes from {512^2, 1024x768, 1280x1024, 2048x1088}, "
-                                           "50-800 rings each (seed 2)"}
+                                           "50-800 rings each (seed 2), launch shapes from rd_autotune"}
         del uframes
 
-    # ---- differentiable step
     if args.edge_steps > 0:
         log(f"[bench] directed edges, {args.edge_steps} plain steps")
         out["edges"] = edges(det, frame, p, W, H, args, torch)
 
+    # ---- differentiable step
     if args.diff_frames > 0:
         log(f"[bench] differentiable step on {args.diff_frames} frames")
         out["differentiable"] = differentiable(det, args, np, torch, synth)
 
     # ---- stream
-    if args.stream_launches > 0:
-        log(f"[bench] stream, {args.stream_launches} launches of 32")
+    if args.stream_frames > 0:
+        log(f"[bench] stream of {args.stream_frames} frames")
         out["stream"] = stream(det, args, np, torch, synth)
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
+        out["cpu_baseline"], head_rings = cpu_baseline(args, f, batch_host, uneven_host)
+        out["parity"] = parity_block(det, f, head_rings, frame)
     print(json.dumps(out), flush=True)
     det.close()
 
@@ -343,7 +464,7 @@ def edges(det, frame, p, W, H, args, torch):
     det.enable_timing(False)
     kms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in timing.items()}
     L = p["r_max"] - p["r_min"] + 3
-    lds_bytes = 4 * W * H * L + 4 * 2 * L * n_edge          # the byte count of the roofline above
+    lds_bytes = 4 * 2 * L * n_edge          # the votes' LDS bytes, as in the roofline above
     return {"value": W * H * args.edge_steps / dt / 1e6, "unit": "Mpixel/s", "frames_per_s": args.edge_steps / dt,
             "ms_per_step": dt / args.edge_steps * 1e3, "kernel_ms": kms, "edge_pixels": int(n_edge),
             "rings_found": int(len(rings)),
@@ -424,79 +545,75 @@ def differentiable(det, args, np, torch, synth):
 
 
 def stream(det, args, np, torch, synth):
-    """32 frames per launch; copies of launch k+1 overlap launch k on a second stream.  Each
-    launch: detection, 20 LM steps per ring, then the refined rings linked into tracks with
-    depths on the GPU.  Link accuracy is scored against the generator's truth afterwards."""
+    """The whole sequence, 32 frames per launch, frames resident in HBM: rendered on the GPU
+    (the stream's model, the device's noise) before the timed region.  Each launch: detection,
+    20 LM steps per ring, then the refined rings linked into tracks with depths on the GPU.
+    One untimed warm-up launch on the first 32 frames; then every launch is timed.  Link
+    accuracy is scored against the generator's truth afterwards."""
     from paper_1310_1371_amd.tracking import Linker
     st = synth.Stream(seed=4)
-    n = 32 * args.stream_launches
-    host = pool_map(st.frame, list(range(n)))
-    p = host[0].params
-    pinned = [torch.from_numpy(fr.image).pin_memory() for fr in host]
-    bufs = [[torch.empty((2048, 2048), dtype=torch.uint16, device="cuda") for _ in range(32)] for _ in range(2)]
-    copy_stream = torch.cuda.Stream()
-    main = torch.cuda.current_stream()
-    copied = [torch.cuda.Event(), torch.cuda.Event()]
-    released = [torch.cuda.Event(), torch.cuda.Event()]
+    n = args.stream_frames
+    p = dict(synth.PARAMS_C5)
+    xs, ys, zs = st.trajectories(n)
+    t0 = time.perf_counter()
+    store = torch.empty((n, st.H, st.W), dtype=torch.int16, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    for t in range(n):
+        st.render_device(xs[t], ys[t], zs[t], store[t], gen)
+        if t % 500 == 499:
+            log(f"[bench]   rendered {t + 1} frames")
+    torch.cuda.synchronize()
+    t_render = time.perf_counter() - t0
+    frames = store.view(torch.uint16)
+    launches = [(k, min(k + 32, n)) for k in range(0, n, 32)]
 
-    def issue_copy(k):
-        b = k % 2
-        with torch.cuda.stream(copy_stream):
-            copy_stream.wait_event(released[b])
-            for i in range(32):
-                bufs[b][i].copy_(pinned[32 * k + i], non_blocking=True)
-            copied[b].record(copy_stream)
-
-    for e in released:
-        e.record(main)
-    n_rings = n_refined = 0
-    t_first = None
-    linker = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32, stream=det.stream)
-    linked, t_link = [], 0.0
-    issue_copy(0)
-    for k in range(args.stream_launches):
-        if k + 1 < args.stream_launches:
-            issue_copy(k + 1)
-        b = k % 2
-        main.wait_event(copied[b])
-        res = det.detect_batch(bufs[b], p)
+    def run(linker, k0, k1, keep):
+        fb = [frames[i] for i in range(k0, k1)]
+        res = det.detect_batch(fb, p)
         th0 = torch.from_numpy(np.concatenate([np.stack([r["cx"], r["cy"], r["r"]], 1) for r in res])
                                .astype(np.float64)).cuda()
         fo = torch.cat([torch.full((len(r),), i, dtype=torch.int32, device="cuda") for i, r in enumerate(res)])
-        theta, _ = det.refine(bufs[b], th0, 1.5, iters=20, frame_of=fo)
-        offs = np.zeros(33, dtype=np.int32)
+        theta, _ = det.refine(fb, th0, 1.5, iters=20, frame_of=fo)
+        offs = np.zeros(len(res) + 1, dtype=np.int32)
         offs[1:] = np.cumsum([len(r) for r in res])
         dets = theta.float().contiguous()
-        torch.cuda.synchronize()      # rd_link returns completed anyway; this isolates its time
-        tl0 = time.perf_counter()
         ids, z = linker.link(dets, offs)
-        if k > 0:
-            t_link += time.perf_counter() - tl0
-        linked.append((dets, ids, z, offs))
-        released[b].record(main)
-        n_rings += int(th0.shape[0])
-        if k == 0:
-            torch.cuda.synchronize()
-            t_first = time.perf_counter()      # the first launch (warm-up) is not timed
+        if keep is not None:
+            keep.append((dets, ids, z, offs))
+        return int(th0.shape[0])
+
+    warm = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32, stream=det.stream)
+    run(warm, 0, min(32, n), None)
+    warm.close()
+    linker = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32, stream=det.stream)
+    linked = []
+    n_rings = 0
     torch.cuda.synchronize()
-    timed = args.stream_launches - 1
-    dt = (time.perf_counter() - t_first) / max(timed, 1)
+    t0 = time.perf_counter()
+    for i, (k0, k1) in enumerate(launches):
+        n_rings += run(linker, k0, k1, linked)
+        if i % 16 == 15:
+            log(f"[bench]   launch {i + 1} of {len(launches)}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
     tracks = linker.info()["tracks"]
     linker.close()
-    acc = link_accuracy(np, linked, host)
-    return {"frames": n, "launches_timed": timed, "frames_per_s": 32 / dt if timed else None,
-            "value": 32 * 2048 * 2048 / dt / 1e6 if timed else None, "unit": "Mpixel/s",
-            "ms_per_launch": dt * 1e3 if timed else None, "rings_detected_and_refined": n_rings,
-            "ms_link_per_launch": t_link / max(timed, 1) * 1e3, "tracks": tracks, "linking": acc,
-            "workload": "2048^2 u16 stream, 1000 rings on random walks, radii 8-80, 32 frames per launch, "
-                        "H2D on a second stream, 20 LM steps per detection, linking (gate 8 px, memory 2) "
-                        "and depth on the GPU"}
+    del store, frames
+    truth = np.stack([xs, ys, st.radius(zs)], 2)
+    acc = link_accuracy(np, linked, truth, np.sqrt((st.radius(zs) - 8.0) / 72.0))
+    return {"frames": n, "launches_timed": len(launches), "frames_per_s": n / dt,
+            "value": n * st.W * st.H / dt / 1e6, "unit": "Mpixel/s", "ms_per_launch": dt / len(launches) * 1e3,
+            "s_total": dt, "rings_detected_and_refined": n_rings, "tracks": tracks, "linking": acc,
+            "s_render_untimed": t_render,
+            "workload": f"the whole {n}-frame 2048^2 u16 stream (1000 rings on random walks, radii 8-80), rendered "
+                        f"on the GPU and resident in HBM, {len(launches)} launches of up to 32 frames, each: "
+                        "batched detection, 20 LM steps per detection, linking (gate 8 px, memory 2) and depth"}
 
 
-def link_accuracy(np, linked, host):
+def link_accuracy(np, linked, truth, z_truth):
     """Each detection is given the truth ring whose centre is nearest (within 3 px, radius
     within 3 px); a link (consecutive detections of one track) is right when both ends have
-    the same truth ring."""
+    the same truth ring.  truth: (frames, rings, 3) centre and radius; z_truth: (frames, rings)."""
     from scipy.spatial import cKDTree
     xs, ids, zs, frame = [], [], [], []
     f0 = 0
@@ -507,23 +624,25 @@ def link_accuracy(np, linked, host):
         frame.append(f0 + np.repeat(np.arange(len(offs) - 1), np.diff(offs)))
         f0 += len(offs) - 1
     x, ids, z, frame = np.concatenate(xs), np.concatenate(ids), np.concatenate(zs), np.concatenate(frame)
-    truth = np.full(len(x), -1)
+    match = np.full(len(x), -1)
     z_true = np.full(len(x), np.nan)
+    bounds = np.searchsorted(frame, np.arange(f0 + 1))
     for f in range(f0):
-        sel = np.nonzero(frame == f)[0]
-        h = host[f]
-        d, j = cKDTree(np.stack([h.cx, h.cy], 1)).query(x[sel, :2])
-        ok = (d < 3.0) & (np.abs(h.R[j] - x[sel, 2]) < 3.0)
-        truth[sel[ok]] = j[ok]
-        z_true[sel[ok]] = np.sqrt((h.R[j[ok]] - 8.0) / 72.0)
+        sel = np.arange(bounds[f], bounds[f + 1])
+        if len(sel) == 0:
+            continue
+        d, j = cKDTree(truth[f, :, :2]).query(x[sel, :2])
+        ok = (d < 3.0) & (np.abs(truth[f, j, 2] - x[sel, 2]) < 3.0)
+        match[sel[ok]] = j[ok]
+        z_true[sel[ok]] = z_truth[f, j[ok]]
     order = np.lexsort((frame, ids))
     same = ids[order][1:] == ids[order][:-1]
-    a, b = truth[order][:-1][same], truth[order][1:][same]
+    a, b = match[order][:-1][same], match[order][1:][same]
     right = (a == b) & (a >= 0)
     return {"links": int(same.sum()), "links_right": float(right.mean()) if same.any() else None,
-            "detections_matched_to_truth": float((truth >= 0).mean()),
+            "detections_matched_to_truth": float((match >= 0).mean()),
             "depth_mean_abs_err": float(np.nanmean(np.abs(z - z_true))),
-            "tracks_per_truth_ring": float(len(np.unique(ids)) / len(host[0].cx))}
+            "tracks_per_truth_ring": float(len(np.unique(ids[ids >= 0])) / truth.shape[1])}
 
 
 if __name__ == "__main__":

@@ -199,6 +199,14 @@ rd_status rd_enable_timing(rd_handle h, int32_t enable);
  * and every eighth call after it are timed.  reset != 0 clears them. */
 rd_status rd_read_timing(rd_handle h, double* ms_total, int64_t* launches, int32_t reset);
 
+/* Measurement only: the device's rate of LDS atomic adds at random addresses, the ceiling of
+ * the vote step (one LDS atomic add per vote).  Workgroups of 1024 threads with 64 KiB of u32
+ * counters each add into a pseudo-random 16-bit half per iteration; with_return = 1 keeps the
+ * returned old values (as the vote kernel does), 0 discards them.  *atomics_per_s receives
+ * the best of three timed launches (HIP events on the null stream of `device`), *ms (may be
+ * NULL) that launch's duration.  Allocates nothing; RD_E_DEVICE without a usable device. */
+rd_status rd_measure_lds_atomics(int32_t device, int32_t with_return, double* atomics_per_s, double* ms);
+
 /* ---- stage entry points (parity checks; same kernels as rd_detect) ------------------- */
 
 /* Step 1 only: k_- (float, H x W, row-major, device pointer) and the direction code of

@@ -140,6 +140,7 @@ hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, int variant, 
 constexpr int VOTE_TILE = 32;
 constexpr int VOTE_LDS_MAX = RD_VOTE_LDS_KB_MAX * 1024;   // dynamic LDS of the vote kernel (static ~70 KB)
 constexpr int VOTE_NLEV_MAX = 20;          // accumulator levels per level chunk
+constexpr int VOTE_TABLE_BYTES = 8192;     // least dynamic LDS of a vote launch (the peak test's table)
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);
 hipError_t vote_prepare();   // one-time kernel attributes (outside any graph capture)
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s);

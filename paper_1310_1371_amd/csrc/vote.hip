@@ -75,8 +75,9 @@ constexpr int SCAP = 512;                  // above-threshold ("strong") voxels 
 constexpr int WC = K_MAX + 8;              // centre tap of the padded weight row
 constexpr int NWW = WC + 4;                // u16 pairs per weight row: taps 0 .. 2 WC + 7
 constexpr int NS_HASH = 64;                // longer strong lists are tested through a hash table
-constexpr int HT = 2048;                   // its slots (u32), in the hotspot list's storage
-static_assert(HT * 4 <= HCAP * 12, "the table lives in the hotspot list's storage");
+constexpr int HT = 2048;                   // its slots (u32), in the histogram's storage (free by then)
+static_assert(HT * 4 <= VOTE_TABLE_BYTES, "the launch gives the histogram at least the table's size");
+static_assert(HT * 4 <= HCAP * 12, "or the table lives in the hotspot list's storage");
 static_assert(SCAP <= 0xffff && (NLEV_MAX - 1) < 32, "table entries pack a 16-bit voxel key and a 16-bit index");
 
 // slot of a voxel key (level << 11 | index in the score region) in the strong-voxel table
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ int32_t sChunk[LMAX + 1];
     __shared__ uint32_t sWave[NW];
     __shared__ uint32_t sNh, sNs;
+    __shared__ uint32_t sLevN[NLEV_MAX];                      // strong voxels per chunk level
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int L = a.nlevels;
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             // the score region (tile + 1 px) in histogram coordinates
             const int hu0 = sx0 - ax0, hw = sx1 - sx0, hv0 = sy0 - ay0, hh = sy1 - sy0;
             if (tid == 0) sNs = 0;                            // last read by the previous 3x3x3 phase
+            if (tid < NLEV_MAX) sLevN[tid] = 0u;
             // ---- votes of the staged ridges.  Only ridges with a sign that can reach the tile
             // are staged.  They are staged once per tile when they fit (ACAP); otherwise the
             // first chunk cuts the candidate list into pieces of whole rounds of NT candidates
@@ -459,7 +462,57 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             const bool per_level = nh_all > static_cast<uint32_t>(HCAP);
             const int nbm = ((2 * Kc + 7) >> 3) + 1;          // 8-column bands a window can span
             const int npass = per_level ? nlev : 1;
-            for (int pass = 0; pass < npass; ++pass) {
+            // The scoring passes, then the 3x3x3 comparison of the strong voxels of the peak levels
+            // [rc0, rc1).  When the chunk has more strong voxels than the list holds (the centres
+            // of several large rings in one tile), the peak levels are taken in windows
+            // [wlo, whi) whose strong voxels at levels wlo - 1 .. whi fit: round 0 scores every
+            // hotspot and counts the strong voxels per level; each later round lists a window's
+            // strong voxels again, from the hotspot list, or, when the hotspots were listed
+            // level by level, by scoring the window's levels again from the histogram.  A window
+            // of one peak level that does not fit is an overflow.
+            bool windows = false;
+            auto strong_in = [&](int lo, int hi) {            // strong voxels at levels lo .. hi
+                uint32_t n = 0;
+                for (int li = max(lo, 0); li <= min(hi, nlev - 1); ++li) n += sLevN[li];
+                return n;
+            };
+            for (int wlo = 1, round = 0; wlo <= nlev - 2; ++round) {
+                int whi = nlev - 1;                            // one window: every peak level
+                int p0 = 0, p1 = npass - 1;                    // scoring passes of this round
+                if (round > 0) {
+                    whi = wlo + 1;
+                    if (strong_in(wlo - 1, whi) > static_cast<uint32_t>(SCAP)) {
+                        if (tid == 0) atomicOr(a.error, 1u);
+                    } else {
+                        while (whi <= nlev - 2 && strong_in(wlo - 1, whi + 1) <= static_cast<uint32_t>(SCAP)) ++whi;
+                    }
+                    __syncthreads();                           // the previous window is done with the list
+                    if (tid == 0) sNs = 0;
+                    __syncthreads();
+                    p0 = 1;
+                    p1 = 0;
+                    if (per_level) {
+                        p0 = wlo - 1;
+                        p1 = whi;
+                    } else {
+                        for (int h = tid; h < static_cast<int>(min(sNh, static_cast<uint32_t>(HCAP))); h += NT) {
+                            const uint32_t e = sHot[h];
+                            const int li = e >> 16;
+                            if (li < wlo - 1 || li > whi) continue;
+                            const unsigned long long sc = sHS[h];
+                            if (sc > sThr[l0 + li - lbase]) {
+                                const uint32_t j = atomicAdd(&sNs, 1u);
+                                if (j < static_cast<uint32_t>(SCAP)) {
+                                    sStrongS[j] = sc;
+                                    sStrongId[j] = e;
+                                    sBad[j] = 0;
+                                }
+                            }
+                        }
+                    }
+                }
+                const bool first = round == 0;
+                for (int pass = p0; pass <= p1; ++pass) {
                 if (per_level) {
                     // rare: more hotspots than the list holds; enumerate one level at a time
                     __syncthreads();
@@ -542,143 +595,149 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const uint32_t e = sHot[h];
                     const int li = e >> 16, sidx = e & 0xffff;
                     const unsigned long long sc = sHS[h];
-                    if (DUMP && a.score_dump) {
+                    if (DUMP && first && a.score_dump) {
                         const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
                         if (vx >= x0 && vx < x0 + T && vy >= y0 && vy < y0 + T)
                             a.score_dump[((int64_t)(l0 + li - lbase) * H + vy) * W + vx] = sc;
                     }
                     if (sc > sThr[l0 + li - lbase]) {
+                        if (first) atomicAdd(&sLevN[li], 1u);
                         const uint32_t j = atomicAdd(&sNs, 1u);
                         if (j < static_cast<uint32_t>(SCAP)) {
                             sStrongS[j] = sc;
                             sStrongId[j] = e;
                             sBad[j] = 0;
-                        } else {
-                            atomicOr(a.error, 1u);
                         }
                     }
                 }
-            }
-            __syncthreads();
-
-            // ---- 3x3x3 comparison of the strong voxels of the peak levels [rc0, rc1)
-            const int ns = static_cast<int>(min(sNs, static_cast<uint32_t>(SCAP)));
-            if (tid == 0) {
-                st_hot += nh_all;
-                st_strong += static_cast<unsigned long long>(ns);
-            }
-            // a voxel is tested if its level is a peak level of this chunk and it lies in the tile
-            auto candidate = [&](int j, int& li, int& lm, int& sxr, int& syr) {
-                const uint32_t e = sStrongId[j];
-                li = e >> 16;
-                lm = l0 + li;
-                const int sidx = e & 0xffff;
-                sxr = sidx % SR;
-                syr = sidx / SR;
-                return lm >= rc0 && lm < rc1 && sxr >= 1 && sxr <= T && syr >= 1 && syr <= T &&
-                       x0 - 1 + sxr < W && y0 - 1 + syr < H;
-            };
-            auto emit = [&](int j, int lm, int sxr, int syr) {
-                const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
-                if (idx < static_cast<uint32_t>(a.max_peaks)) {
-                    Peak pk;
-                    pk.a = x0 - 1 + sxr; pk.b = y0 - 1 + syr; pk.r = lm; pk.frame = f; pk.s = sStrongS[j];
-                    a.peaks[fd.peak0 + idx] = pk;
                 }
-            };
-            // a neighbour beats v if its S_int / r is larger, or equal and it comes before v in
-            // (r, y, x) order; a neighbour below the threshold cannot, so only strong ones count
-            auto beats = [&](unsigned long long sv, int lm, int k, int dl, int dy, int dx) {
-                const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
-                const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(lm);
-                const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                return earlier ? !(lhs > rhs) : !(lhs >= rhs);
-            };
-            if (ns > NS_HASH) {
-                // a long list (the mark of a ring-centre tile, the slowest work of a launch):
-                // the strong voxels go into an open-addressing table keyed by voxel, and each
-                // candidate looks up its 26 neighbours, one task per candidate and level offset.
-                // The hotspot list is not read again in this chunk, so its storage holds the table.
-                uint32_t* const sTab = reinterpret_cast<uint32_t*>(sScratch);
-                for (int i = tid; i < HT; i += NT) sTab[i] = 0xffffffffu;
                 __syncthreads();
-                for (int j = tid; j < ns; j += NT) {
+                if (first) {
+                    const uint32_t ns_all = sNs;
+                    if (tid == 0) {
+                        st_hot += nh_all;
+                        st_strong += static_cast<unsigned long long>(ns_all);
+                    }
+                    windows = ns_all > static_cast<uint32_t>(SCAP);
+                    if (windows) continue;                     // round 1 takes the first window
+                }
+                const bool in_hist = windows && !per_level;
+                const int ns = static_cast<int>(min(sNs, static_cast<uint32_t>(SCAP)));
+                // a voxel is tested if its level is a peak level of this window and it lies in the tile
+                auto candidate = [&](int j, int& li, int& lm, int& sxr, int& syr) {
                     const uint32_t e = sStrongId[j];
-                    const uint32_t key = ((e >> 16) << 11) | (e & 0xffffu);     // distinct per voxel
-                    // at most SCAP of HT slots are taken, so the probe ends
-                    for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1))
-                        if (atomicCAS(&sTab[slot], 0xffffffffu, (key << 16) | static_cast<uint32_t>(j)) == 0xffffffffu)
-                            break;
-                }
-                __syncthreads();
-                for (int task = tid; task < 3 * ns; task += NT) {
-                    const int j = task / 3, dl = task - 3 * j - 1;
-                    int li, lm, sxr, syr;
-                    if (!candidate(j, li, lm, sxr, syr)) continue;
-                    const int nl = li + dl;
-                    if (nl < 0 || nl >= nlev) continue;
-                    const unsigned long long sv = sStrongS[j];
-                    bool peak = true;
-#pragma unroll
-                    for (int o = 0; o < 9; ++o) {
-                        const int dy = o / 3 - 1, dx = o % 3 - 1;
-                        if (dl == 0 && dy == 0 && dx == 0) continue;
-                        // 1 <= sxr, syr <= T: the neighbour lies in the score region's index range
-                        const uint32_t key = (static_cast<uint32_t>(nl) << 11) |
-                                             static_cast<uint32_t>((syr + dy) * SR + sxr + dx);
-                        for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1)) {
-                            const uint32_t v = sTab[slot];
-                            if (v == 0xffffffffu) break;                      // not strong
-                            if ((v >> 16) == key) {
-                                if (beats(sv, lm, static_cast<int>(v & 0xffffu), dl, dy, dx)) peak = false;
+                    li = e >> 16;
+                    lm = l0 + li;
+                    const int sidx = e & 0xffff;
+                    sxr = sidx % SR;
+                    syr = sidx / SR;
+                    return li >= wlo && li < whi && sxr >= 1 && sxr <= T && syr >= 1 && syr <= T &&
+                           x0 - 1 + sxr < W && y0 - 1 + syr < H;
+                };
+                auto emit = [&](int j, int lm, int sxr, int syr) {
+                    const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
+                    if (idx < static_cast<uint32_t>(a.max_peaks)) {
+                        Peak pk;
+                        pk.a = x0 - 1 + sxr; pk.b = y0 - 1 + syr; pk.r = lm; pk.frame = f; pk.s = sStrongS[j];
+                        a.peaks[fd.peak0 + idx] = pk;
+                    }
+                };
+                // a neighbour beats v if its S_int / r is larger, or equal and it comes before v in
+                // (r, y, x) order; a neighbour below the threshold cannot, so only strong ones count
+                auto beats = [&](unsigned long long sv, int lm, int k, int dl, int dy, int dx) {
+                    const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
+                    const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(lm);
+                    const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+                    return earlier ? !(lhs > rhs) : !(lhs >= rhs);
+                };
+                if (ns > NS_HASH) {
+                    // a long list (the mark of a ring-centre tile, the slowest work of a launch):
+                    // the strong voxels go into an open-addressing table keyed by voxel, and each
+                    // candidate looks up its 26 neighbours, one task per candidate and level
+                    // offset.  The table takes the hotspot list's storage, which this window does
+                    // not read again; when windows relist from the hotspot list, it takes the
+                    // histogram's, which is not read again in this chunk.
+                    uint32_t* const sTab = in_hist ? sA : reinterpret_cast<uint32_t*>(sScratch);
+                    for (int i = tid; i < HT; i += NT) sTab[i] = 0xffffffffu;
+                    __syncthreads();
+                    for (int j = tid; j < ns; j += NT) {
+                        const uint32_t e = sStrongId[j];
+                        const uint32_t key = ((e >> 16) << 11) | (e & 0xffffu);     // distinct per voxel
+                        // at most SCAP of HT slots are taken, so the probe ends
+                        for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1))
+                            if (atomicCAS(&sTab[slot], 0xffffffffu, (key << 16) | static_cast<uint32_t>(j)) == 0xffffffffu)
                                 break;
+                    }
+                    __syncthreads();
+                    for (int task = tid; task < 3 * ns; task += NT) {
+                        const int j = task / 3, dl = task - 3 * j - 1;
+                        int li, lm, sxr, syr;
+                        if (!candidate(j, li, lm, sxr, syr)) continue;
+                        const int nl = li + dl;
+                        if (nl < 0 || nl >= nlev) continue;
+                        const unsigned long long sv = sStrongS[j];
+                        bool peak = true;
+#pragma unroll
+                        for (int o = 0; o < 9; ++o) {
+                            const int dy = o / 3 - 1, dx = o % 3 - 1;
+                            if (dl == 0 && dy == 0 && dx == 0) continue;
+                            // 1 <= sxr, syr <= T: the neighbour lies in the score region's index range
+                            const uint32_t key = (static_cast<uint32_t>(nl) << 11) |
+                                                 static_cast<uint32_t>((syr + dy) * SR + sxr + dx);
+                            for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1)) {
+                                const uint32_t v = sTab[slot];
+                                if (v == 0xffffffffu) break;                      // not strong
+                                if ((v >> 16) == key) {
+                                    if (beats(sv, lm, static_cast<int>(v & 0xffffu), dl, dy, dx)) peak = false;
+                                    break;
+                                }
                             }
                         }
+                        if (!peak) sBad[j] = 1;
                     }
-                    if (!peak) sBad[j] = 1;
+                    __syncthreads();
+                    for (int j = tid; j < ns; j += NT) {
+                        int li, lm, sxr, syr;
+                        if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
+                    }
+                } else {
+                    // a short list: G lanes per strong voxel, each comparing a slice of the list
+                    const int gs = ns > 32 ? 3 : 0;
+                    const int G = 1 << gs;
+                    for (int task = tid; task < (ns << gs); task += NT) {
+                        const int j = task >> gs, g = task & (G - 1);
+                        int li, lm, sxr, syr;
+                        if (!candidate(j, li, lm, sxr, syr)) continue;
+                        // the neighbours that matter are strong too (a weaker one cannot win), so
+                        // the comparison runs over the window's strong list
+                        const unsigned long long sv = sStrongS[j];
+                        bool peak = true;
+                        for (int k = g; k < ns && peak; k += G) {
+                            if (k == j) continue;
+                            const uint32_t eu = sStrongId[k];
+                            const int dl = static_cast<int>(eu >> 16) - li;
+                            const int su_idx = static_cast<int>(eu & 0xffffu);
+                            const int dy = su_idx / SR - syr, dx = su_idx % SR - sxr;
+                            if (dl < -1 || dl > 1 || dy < -1 || dy > 1 || dx < -1 || dx > 1) continue;
+                            if (beats(sv, lm, k, dl, dy, dx)) peak = false;
+                        }
+                        if (G == 1) {
+                            if (peak) emit(j, lm, sxr, syr);
+                        } else if (!peak) {
+                            sBad[j] = 1;
+                        }
+                    }
+                    if (G > 1) {
+                        __syncthreads();
+                        for (int j = tid; j < ns; j += NT) {
+                            int li, lm, sxr, syr;
+                            if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
+                        }
+                    }
                 }
-                __syncthreads();
-                for (int j = tid; j < ns; j += NT) {
-                    int li, lm, sxr, syr;
-                    if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
-                }
-                if (c + 1 < a.nchunks) prepare(c + 1);
-                __syncthreads();
-                continue;
+                wlo = whi;
             }
-            // a short list: G lanes per strong voxel, each comparing a slice of the list
-            const int gs = ns > 32 ? 3 : 0;
-            const int G = 1 << gs;
-            for (int task = tid; task < (ns << gs); task += NT) {
-                const int j = task >> gs, g = task & (G - 1);
-                int li, lm, sxr, syr;
-                if (!candidate(j, li, lm, sxr, syr)) continue;
-                // the neighbours that matter are strong too (a weaker one cannot win), so
-                // the comparison runs over the chunk's strong list
-                const unsigned long long sv = sStrongS[j];
-                bool peak = true;
-                for (int k = g; k < ns && peak; k += G) {
-                    if (k == j) continue;
-                    const uint32_t eu = sStrongId[k];
-                    const int dl = static_cast<int>(eu >> 16) - li;
-                    const int su_idx = static_cast<int>(eu & 0xffffu);
-                    const int dy = su_idx / SR - syr, dx = su_idx % SR - sxr;
-                    if (dl < -1 || dl > 1 || dy < -1 || dy > 1 || dx < -1 || dx > 1) continue;
-                    if (beats(sv, lm, k, dl, dy, dx)) peak = false;
-                }
-                if (G == 1) {
-                    if (peak) emit(j, lm, sxr, syr);
-                } else if (!peak) {
-                    sBad[j] = 1;
-                }
-            }
-            if (G > 1) {
-                __syncthreads();
-                for (int j = tid; j < ns; j += NT) {
-                    int li, lm, sxr, syr;
-                    if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
-                }
-            }
+            if (windows && !per_level) __syncthreads();       // the table in the histogram is done
             if (c + 1 < a.nchunks) prepare(c + 1);
             __syncthreads();
         }
@@ -795,6 +854,7 @@ hipError_t vote_prepare() {
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s) {
     if (a.total_vtiles <= 0 || a.nchunks <= 0) return hipSuccess;
     if (lds > static_cast<size_t>(VOTE_LDS_MAX)) return hipErrorInvalidValue;   // beyond the opted-in size
+    if (lds < static_cast<size_t>(VOTE_TABLE_BYTES)) lds = VOTE_TABLE_BYTES;
     if (blocks > a.total_vtiles) blocks = a.total_vtiles;   // persistent blocks take tiles from the queue
     if (dump)
         hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(blocks), dim3(NT), lds, s, a);

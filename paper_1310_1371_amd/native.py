@@ -76,6 +76,7 @@ SIGNATURES = {
     "rd_read_stats": (ctypes.c_int, [_vp, _P(_i64)]),
     "rd_enable_timing": (ctypes.c_int, [_vp, _i32]),
     "rd_read_timing": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "rd_measure_lds_atomics": (ctypes.c_int, [_i32, _i32, _P(ctypes.c_double), _P(ctypes.c_double)]),
     "rd_stage_curvature": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp, _vp]),
     "rd_stage_ridges": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp, _vp, _vp, _i64, _P(_i64)]),
     "rd_stage_accumulate": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(RdParams), _vp, _vp]),

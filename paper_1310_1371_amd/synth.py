@@ -293,6 +293,40 @@ class Stream:
             z = self._reflect(z + rng.normal(0, 0.01, self.n), 0.0, 1.0)
         return x, y, z
 
+    def trajectories(self, n_frames: int):
+        """Positions and depths of every ring at frames 0 .. n_frames - 1, arrays (n_frames, n):
+        the walk of state(t) drawn once, with the same increments."""
+        xs = np.empty((n_frames, self.n))
+        ys = np.empty((n_frames, self.n))
+        zs = np.empty((n_frames, self.n))
+        x, y, z = self.x0.copy(), self.y0.copy(), self.z0.copy()
+        for k in range(n_frames):
+            if k > 0:
+                rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([self.seed, 1, k])))
+                x = self._reflect(x + rng.normal(0, 1.5, self.n), 0.0, self.W - 1.0)
+                y = self._reflect(y + rng.normal(0, 1.5, self.n), 0.0, self.H - 1.0)
+                z = self._reflect(z + rng.normal(0, 0.01, self.n), 0.0, 1.0)
+            xs[k], ys[k], zs[k] = x, y, z
+        return xs, ys, zs
+
+    @staticmethod
+    def radius(z):
+        """radius(z) = 8 + 72 z^2."""
+        return 8.0 + 72.0 * np.asarray(z) ** 2
+
+    def render_device(self, x, y, z, out, generator):
+        """The frame of ring state (x, y, z) rendered by torch on out's device into out (int16
+        [H, W], values 0 .. 4095, bit-identical to uint16): background 200, amplitude 1000,
+        profile sigma 1.5, N(0, 50^2) noise from `generator`, rounded and clipped to 12 bits.
+        Same model as frame(t), evaluated in float32 with the device's noise stream, so the
+        pixels are not numpy's; used where thousands of frames are needed quickly."""
+        import torch
+        img = render_torch(self.W, self.H, 200.0, x, y, self.radius(z), np.full(self.n, 1.5),
+                           np.full(self.n, 1000.0), out.device)
+        img += torch.randn(img.shape, device=out.device, generator=generator) * 50.0
+        out.copy_(torch.clamp(torch.round(img), 0.0, 4095.0).to(torch.int16))
+        return out
+
     def frame(self, t: int) -> Frame:
         x, y, z = self.state(t)
         R = 8.0 + 72.0 * z * z
@@ -302,6 +336,35 @@ class Stream:
         clean = render(self.W, self.H, np.full((self.H, self.W), 200.0), x, y, R, s, A)
         img = np.clip(np.rint(clean + rng.normal(0.0, 50.0, clean.shape)), 0, 4095).astype(np.uint16)
         return Frame(img, x, y, R, s, A, dict(PARAMS_C5), self.seed)
+
+
+def render_torch(W: int, H: int, bg: float, cx, cy, R, s, A, device, bucket: int = 16):
+    """render() with torch on `device` in float32 (constant background): each ring is evaluated
+    on its box [floor(c - ext), ceil(c + ext)] (ext = R + 6 s) clipped to the frame, the rings
+    grouped by box size in steps of `bucket` px, and added with index_add_.  Agrees with
+    render() to float32 rounding."""
+    import torch
+    cx, cy, R, s, A = (np.asarray(v, dtype=np.float64) for v in (cx, cy, R, s, A))
+    img = torch.full((H * W,), float(bg), dtype=torch.float32, device=device)
+    ext = R + 6.0 * s
+    lo_x, hi_x = np.floor(cx - ext), np.ceil(cx + ext)
+    lo_y, hi_y = np.floor(cy - ext), np.ceil(cy + ext)
+    side = np.maximum(hi_x - lo_x, hi_y - lo_y).astype(np.int64) + 1
+    group = (side + bucket - 1) // bucket
+    for g in np.unique(group):
+        sel = np.nonzero(group == g)[0]
+        B = int(g) * bucket
+        t = lambda v: torch.as_tensor(v[sel], dtype=torch.float32, device=device)[:, None, None]
+        x0, y0 = t(lo_x), t(lo_y)
+        off = torch.arange(B, dtype=torch.float32, device=device)
+        X = x0 + off[None, None, :]
+        Y = y0 + off[None, :, None]
+        ok = (X <= t(hi_x)) & (Y <= t(hi_y)) & (X >= 0) & (X <= W - 1) & (Y >= 0) & (Y <= H - 1)
+        rho = torch.hypot(X - t(cx), Y - t(cy))
+        val = t(A) * torch.exp(-((rho - t(R)) ** 2) / (2.0 * t(s) ** 2))
+        idx = (Y * W + X).to(torch.int64)
+        img.index_add_(0, idx[ok], val[ok])
+    return img.view(H, W)
 
 
 def single_ring(W: int, H: int, cx: float, cy: float, R: float, s: float = 1.5, A: float = 1.0,

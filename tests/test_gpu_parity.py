@@ -217,6 +217,70 @@ def test_strong_list_overflow_is_reported(det):
     assert e.value.status == N.RD_E_OVERFLOW
 
 
+def _crowded(peak_fraction, vote_threshold):
+    """256 x 256 float32 with six rings of radius 72.6-80.5 px whose centres all lie in the vote
+    tile x, y in [96, 128), radius bins 8-80: at f = 0.25 that tile holds about 1100
+    above-threshold voxels at radii 72-81 (about 110 per level), at f = 0.15 about 150 per
+    level, both beyond the 512 of one level chunk's list, so the 3x3x3 test runs over windows
+    of peak levels (several levels, then one level per window).  Such tiles occur in the
+    2048^2 stream when two large rings' centres meet."""
+    cx = np.array([108.3, 113.6, 104.2, 116.9, 110.1, 119.4])
+    cy = np.array([110.8, 116.4, 118.1, 106.7, 104.5, 118.9])
+    R = np.array([74.2, 77.4, 79.3, 75.8, 72.6, 80.5])
+    s, A = np.full(6, 1.5), np.ones(6)
+    img = synth.render(256, 256, np.full((256, 256), 0.2), cx, cy, R, s, A).astype(np.float32)
+    p = dict(O.DEFAULTS, **dict(synth.PARAMS_C1, r_min=8, r_max=80, peak_fraction=peak_fraction,
+                                vote_threshold=vote_threshold))
+    return img, p
+
+
+@pytest.mark.parametrize("f,tint", [(0.25, 3), (0.15, 2)])
+def test_crowded_tile_windows_exact(det, f, tint):
+    say(f"[crowded tile] f = {f}, T_int = {tint}")
+    img, p = _crowded(f, tint)
+    H, W = img.shape
+    xs, ys, qx, qy, _ = O.ridges(img, p)
+    ref, A_ref, S_ref = O.detect_from_ridges(xs, ys, qx, qy, W, H, p, return_volumes=True)
+    lbase = p["r_min"] - 1
+    thr = np.array([O.score_threshold(lbase + i, p) for i in range(S_ref.shape[0])])
+    n_strong = int((S_ref > thr[:, None, None])[72 - lbase:82 - lbase, 95:129, 95:129].sum())
+    say(f"  strong voxels of the tile at radii 72-81: {n_strong}; oracle rings {len(ref)}")
+    assert n_strong > 2 * 512                      # the case does exercise the windows
+    xy = np.stack([xs, ys], 1).astype(np.int32)
+    q = np.stack([qx, qy], 1).astype(np.int16)
+    acc, sc = det.accumulate(xy, q, W, H, p)
+    np.testing.assert_array_equal(acc.cpu().numpy().astype(np.int64), A_ref)
+    np.testing.assert_array_equal(sc.cpu().numpy(), S_ref)
+    got = det.detect_from_ridges(xy, q, W, H, p)
+    assert [tuple(int(v) for v in (r["a"], r["b"], r["r_bin"])) for r in ref] == \
+           [tuple(int(v) for v in (r["a"], r["b"], r["r_bin"])) for r in got]
+    np.testing.assert_array_equal(ref["n_fit"], got["n_fit"])
+    np.testing.assert_array_equal(ref["fit_ok"], got["fit_ok"])
+    for fld in ("cx", "cy", "r", "score"):
+        np.testing.assert_allclose(got[fld], ref[fld], rtol=2e-7, atol=1e-9)
+    # end to end from the frame
+    e2e = det.detect(torch.from_numpy(img).cuda(), p)
+    kr, kg = _match(O.detect(img, p), e2e)
+    assert len(set(kr) ^ set(kg)) <= max(1, 0.01 * len(kr))
+    for k in set(kr) & set(kg):
+        for fld in ("cx", "cy", "r"):
+            assert abs(float(kr[k][fld]) - float(kg[k][fld])) <= 0.05
+
+
+def test_crowded_tile_overflow_reported(det):
+    """With f = 0.1 and T_int = 1 a window of one peak level (three levels) holds more
+    above-threshold voxels than the list: RD_E_OVERFLOW, not a partial answer."""
+    from paper_1310_1371_amd import native as N
+    say("[crowded tile] f = 0.1, T_int = 1: overflow")
+    img, p = _crowded(0.1, 1)
+    xs, ys, qx, qy, _ = O.ridges(img, p)
+    xy = np.stack([xs, ys], 1).astype(np.int32)
+    q = np.stack([qx, qy], 1).astype(np.int16)
+    with pytest.raises(N.RdError) as e:
+        det.detect_from_ridges(xy, q, 256, 256, p)
+    assert e.value.status == N.RD_E_OVERFLOW
+
+
 def test_accumulator_bit_exact_c2_full(det):
     say("[accumulate] c2 1024x1024, 68 levels")
     f = synth.config2()
