@@ -29,7 +29,7 @@ TWO_PI = 6.283185307179586
 
 DEFAULTS = dict(sigma_smooth=2.0, k_threshold=-0.02, r_min=8, r_max=40, vote_threshold=3,
                 peak_fraction=0.4, sig_slope=0.05, sig_icpt=0.25, annulus_halfwidth=2,
-                min_fit_points=8, measure=0)
+                min_fit_points=8, measure=0, r_step=1)
 MEASURE_RIDGE, MEASURE_EDGE = 0, 1     # directed ridges (Hessian) or directed edges (gradient)
 
 
@@ -221,6 +221,19 @@ def ridges(img, params):
 # votes over [r_min - 1, r_max + 1], peaks searched in [r_min, r_max])
 # --------------------------------------------------------------------------------------
 
+def level_radii(p) -> np.ndarray:
+    """Radii of the accumulator levels.  The paper votes over [r_min - 1, r_max + 1] in steps
+    of one pixel and searches peaks in [r_min, r_max] (SI, "Additional notes"), and names a
+    coarser discretisation of the circle parameter space as a way to trade accuracy for speed
+    (same notes).  READING for a radius step s >= 1: the peak levels are r_min, r_min + s,
+    ... up to r_max, with one more level a step beyond each end, so level l has radius
+    r_min - s + s l, l = 0 .. L - 1, L = floor((r_max - r_min) / s) + 3.  s = 1 is the plain
+    method."""
+    s = int(p.get("r_step", 1))
+    L = (int(p["r_max"]) - int(p["r_min"])) // s + 3
+    return int(p["r_min"]) - s + s * np.arange(L, dtype=np.int64)
+
+
 def vote_offset(r, q):
     """READING: rho(r, q) = floor((r q + 2^13) / 2^14), the fixed-point r X_- rounded
     half up."""
@@ -228,14 +241,19 @@ def vote_offset(r, q):
 
 
 def vote(xs, ys, qx, qy, W, H, r_lo, r_hi):
-    """Dense integer accumulator A[r - r_lo, b, a] over levels r_lo..r_hi.  Votes whose
-    centre falls outside the frame are dropped (READING)."""
-    L = r_hi - r_lo + 1
+    """Dense integer accumulator A[r - r_lo, b, a] over levels r_lo..r_hi."""
+    return vote_radii(xs, ys, qx, qy, W, H, np.arange(r_lo, r_hi + 1))
+
+
+def vote_radii(xs, ys, qx, qy, W, H, radii):
+    """Dense integer accumulator A[l, b, a] at the level radii `radii`.  Votes whose centre
+    falls outside the frame are dropped (READING)."""
+    L = len(radii)
     A = np.zeros((L, H, W), dtype=np.int64)
     xs = np.asarray(xs, dtype=np.int64)
     ys = np.asarray(ys, dtype=np.int64)
     for li in range(L):
-        r = r_lo + li
+        r = int(radii[li])
         ox = vote_offset(r, qx)
         oy = vote_offset(r, qy)
         for s in (1, -1):
@@ -320,12 +338,18 @@ def smooth_level_exact(A_r, hot, r, p):
 
 
 def smooth(A, r_lo, p):
-    """Integer scores for every level of the accumulator (0 off hotspots)."""
+    """Integer scores for every level of the accumulator (0 off hotspots), levels r_lo, r_lo + 1, ..."""
+    return smooth_radii(A, r_lo + np.arange(A.shape[0]), p)
+
+
+def smooth_radii(A, radii, p):
+    """Integer scores for every level (0 off hotspots); level l has radius radii[l] and is
+    smoothed within itself with that radius' window."""
     S = np.zeros(A.shape, dtype=np.int64)
     for li in range(A.shape[0]):
         hot = hotspots(A[li], int(p["vote_threshold"]))
         if np.any(hot):
-            S[li] = smooth_level_int(A[li], hot, r_lo + li, p)
+            S[li] = smooth_level_int(A[li], hot, int(radii[li]), p)
     return S
 
 
@@ -335,16 +359,22 @@ def smooth(A, r_lo, p):
 # --------------------------------------------------------------------------------------
 
 def peaks(S, r_lo, p):
-    """Candidates: r in [r_min, r_max], S > f 2 pi.  A candidate v is a peak if
-    S(v) >= S(u) for all 26 neighbours u in the volume and S(v) > S(u) for those u before v
-    in (r, y, x) order (READING: the tie-break keeps a plateau's first voxel).  Scores at
-    different levels compare as S_int / r, done exactly by cross-multiplication.
+    """peaks_radii on levels of radius r_lo, r_lo + 1, ..."""
+    return peaks_radii(S, r_lo + np.arange(S.shape[0]), p)
+
+
+def peaks_radii(S, radii, p):
+    """Candidates: level radius r in [r_min, r_max], S > f 2 pi.  A candidate v is a peak if
+    S(v) >= S(u) for all 26 neighbours u in the volume (the adjacent levels, whatever their
+    radii) and S(v) > S(u) for those u before v in (level, y, x) order (READING: the
+    tie-break keeps a plateau's first voxel).  Scores at different levels compare as
+    S_int / r, done exactly by cross-multiplication with the levels' radii.
     Returns int64 arrays (a, b, r, S_int) in ascending (r, b, a)."""
     L, H, W = S.shape
     r_min, r_max = int(p["r_min"]), int(p["r_max"])
     out = []
     for li in range(L):
-        r = r_lo + li
+        r = int(radii[li])
         if r < r_min or r > r_max:
             continue
         thr = score_threshold(r, p)
@@ -356,7 +386,7 @@ def peaks(S, r_lo, p):
                 lj = li + dl
                 if lj < 0 or lj >= L:
                     continue
-                ru = r_lo + lj
+                ru = int(radii[lj])
                 for dy in (-1, 0, 1):
                     yy = y + dy
                     if yy < 0 or yy >= H:
@@ -461,10 +491,10 @@ def fit_rings(xs, ys, pa, pb, pr, pS, p):
 
 def detect_from_ridges(xs, ys, qx, qy, W, H, params, return_volumes=False):
     p = dict(DEFAULTS, **params)
-    r_lo, r_hi = int(p["r_min"]) - 1, int(p["r_max"]) + 1
-    A = vote(xs, ys, qx, qy, W, H, r_lo, r_hi)
-    S = smooth(A, r_lo, p)
-    pa, pb, pr, pS = peaks(S, r_lo, p)
+    radii = level_radii(p)
+    A = vote_radii(xs, ys, qx, qy, W, H, radii)
+    S = smooth_radii(A, radii, p)
+    pa, pb, pr, pS = peaks_radii(S, radii, p)
     rings = fit_rings(xs, ys, pa, pb, pr, pS, p)
     if return_volumes:
         return rings, A, S
