@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--uneven", type=int, default=64, help="frames of the uneven batch (0: skip)")
     ap.add_argument("--edge-steps", type=int, default=100, help="plain steps with directed edges (0: skip)")
+    ap.add_argument("--step-steps", type=int, default=100,
+                    help="plain steps per radius step s = 1, 2, 3 (0: skip)")
     ap.add_argument("--diff-frames", type=int, default=16, help="frames of the differentiable step (0: skip)")
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--stream-frames", type=int, default=2000, help="frames of the stream, 32 per launch (0: skip)")
@@ -427,6 +429,10 @@ def main():
         log(f"[bench] directed edges, {args.edge_steps} plain steps")
         out["edges"] = edges(det, frame, p, W, H, args, torch)
 
+    if args.step_steps > 0:
+        log(f"[bench] radius steps 1-3, {args.step_steps} plain steps each")
+        out["radius_step"] = radius_step(det, frame, f, args, np, torch)
+
     # ---- differentiable step
     if args.diff_frames > 0:
         log(f"[bench] differentiable step on {args.diff_frames} frames")
@@ -471,6 +477,50 @@ def edges(det, frame, p, W, H, args, torch):
             "vote_roofline_frac": lds_bytes / (kms["vote"] * 1e-3) / 1e9 / LDS_PEAK_GBS,
             "workload": "plain rd_detect with directed edges (measure 1, T = -12 counts/px) on the same "
                         "1024x1024 u16 frame"}
+
+
+def radius_step(det, frame, f, args, np, torch):
+    """The plain path on the headline frame with the radius levels in steps of s = 1, 2, 3
+    (levels r_min - s + s l): throughput, the vote kernel's time, and the rings against the
+    generator's truth (a ring is found when a detection lies within 2 px of its centre and
+    2 px + s/2 of its radius; errors are means over the found rings)."""
+    out = {}
+    truth = np.stack([f.cx, f.cy, f.R], 1)
+    H, W = f.image.shape
+    for s in (1, 2, 3):
+        ps = dict(f.params, r_step=s, annulus_halfwidth=max(2, (s + 1) // 2 + 1))
+        for _ in range(5):
+            rings = det.detect(frame, ps)
+        det.enable_timing(True)
+        det.read_timing(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.step_steps):
+            rings = det.detect(frame, ps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        timing = det.read_timing(reset=True)
+        det.enable_timing(False)
+        found = np.stack([rings["cx"], rings["cy"], rings["r"]], 1).astype(np.float64)
+        err = []
+        hit = set()
+        for j in range(len(truth)):
+            d = np.hypot(found[:, 0] - truth[j, 0], found[:, 1] - truth[j, 1])
+            k = int(np.argmin(d)) if len(d) else -1
+            if k >= 0 and d[k] <= 2.0 and abs(found[k, 2] - truth[j, 2]) <= 2.0 + s / 2:
+                hit.add(j)
+                err.append(np.abs(found[k] - truth[j]))
+        err = np.array(err)
+        out[f"s{s}"] = {"value": W * H * args.step_steps / dt / 1e6, "unit": "Mpixel/s",
+                        "frames_per_s": args.step_steps / dt,
+                        "vote_ms": timing["vote"][0] / max(timing["vote"][1], 1),
+                        "levels": (ps["r_max"] - ps["r_min"]) // s + 3, "annulus_halfwidth": ps["annulus_halfwidth"],
+                        "rings_found": int(len(rings)), "truth_found": len(hit), "truth": int(len(truth)),
+                        "mean_abs_err_px": {"cx": float(err[:, 0].mean()), "cy": float(err[:, 1].mean()),
+                                            "r": float(err[:, 2].mean())} if len(err) else None}
+    out["workload"] = ("plain rd_detect on the headline 1024x1024 u16 frame with radius levels in steps of s "
+                       "(r_step), annulus half-width max(2, ceil(s/2) + 1); accuracy against the generator's rings")
+    return out
 
 
 def differentiable(det, args, np, torch, synth):

@@ -79,7 +79,7 @@ typedef struct {
                                  scale selection at about the outer ring's scale)          */
     float k_threshold;        /* threshold T_k <= 0 on the measure: curvature, image units /
                                  px^2 (SI step 2); with directed edges -|grad I|, units / px */
-    int32_t r_min, r_max;     /* radius range, 1 <= r_min <= r_max <= 126, step 1 px       */
+    int32_t r_min, r_max;     /* radius range, r_min <= r_max <= 126, searched in steps of r_step */
     int32_t vote_threshold;   /* integer hotspot threshold: A > vote_threshold (SI step 4) */
     float peak_fraction;      /* f: a peak needs S > f * 2 pi (SI step 4), 0 <= f          */
     float sig_slope;          /* sigma(r) = sig_slope * r + sig_icpt (Methods: 0.05, 0.25) */
@@ -88,6 +88,16 @@ typedef struct {
     int32_t min_fit_points;   /* fewer annulus members than this: fit_ok = 0, >= 3         */
     int32_t measure;          /* RD_MEASURE_RIDGE or RD_MEASURE_EDGE; the differentiable
                                  entry points (rd_soft_*, rd_hessian_backward) take ridges only */
+    int32_t r_step;           /* radius step s of the accumulator levels, 0 <= s <= 16 (0 reads
+                                 as 1): level l has radius r_min - s + s l, l = 0 .. L - 1 with
+                                 L = (r_max - r_min) / s + 3, so the peak levels are r_min,
+                                 r_min + s, ... <= r_max with one level a step beyond each end
+                                 (SI, "Additional notes": a lower resolution of the circle
+                                 parameter space).  r_min - s >= 1 (every level has a radius of
+                                 at least 1, as scores compare across levels as S / r) and the
+                                 top level's radius <= 127.  s = 1 is the plain method.  The annulus half-width
+                                 should cover half a step (w >= s / 2 + 1).  rd_soft_forward and
+                                 rd_soft_backward take s = 1 only. */
 } rd_params;
 
 /* One detected ring.  (a, b, r_bin) is the Hough peak voxel; (cx, cy, r) the circle fit
@@ -118,9 +128,10 @@ const char* rd_status_string(rd_status s);
 /* Host-only check of a parameter set; no device needed. */
 rd_status rd_validate_params(const rd_params* p);
 
-/* Host-only: the per-level tables the library derives from *p for radii r_min - 1 ..
- * r_max + 1 (L = r_max - r_min + 3 levels; caller arrays of at least L entries, wtab of
- * L * 25): ktab[i] = K(r) = ceil(3 sigma(r)), sigma(r) = sig_slope r + sig_icpt in double;
+/* Host-only: the per-level tables the library derives from *p for the level radii
+ * r = r_min - s + s i, i = 0 .. L - 1 (s = r_step, L = (r_max - r_min) / s + 3; caller arrays
+ * of at least L entries, wtab of L * 25): ktab[i] = K(r) = ceil(3 sigma(r)),
+ * sigma(r) = sig_slope r + sig_icpt in double;
  * wtab[i * 25 + d] = floor(2^15 exp(-d^2 / (2 sigma(r)^2)) + 1/2) for d <= K(r), else 0
  * (the separable fixed-point smoothing factors, Methods "Algorithm implementation");
  * thr[i] = floor(((f * 2 pi) * r) * 2^30), so that S > f 2 pi <=> S_int > thr (SI step 4).
@@ -236,8 +247,8 @@ rd_status rd_validate_ridges(const int32_t* xy, const int16_t* q, int64_t n, int
  * pairs and q_dev = (qx, qy) int16 pairs for n ridges (device pointers; the list must pass
  * the test of rd_validate_ridges, checked on the device: RD_E_INVALID otherwise; any order,
  * e.g. the bin order of rd_stage_ridges or raster order).  acc_dev receives the dense vote
- * accumulator, uint32 [L][height][width] with L = r_max - r_min + 3 levels for radii
- * r_min - 1 .. r_max + 1.  score_dev (may be NULL) receives the integer smoothed score
+ * accumulator, uint32 [L][height][width], level i at radius r_min - s + s i
+ * (L = (r_max - r_min) / s + 3, s = r_step).  score_dev (may be NULL) receives the integer smoothed score
  * S_int = sum W(|dx|) W(|dy|) A (W = 15-bit fixed-point Gaussian factors) at hotspots and
  * 0 elsewhere, uint64 [L][height][width]; the score is S = S_int / (r 2^30). */
 rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t* q_dev,

@@ -228,7 +228,10 @@ def level_radii(p) -> np.ndarray:
     (same notes).  READING for a radius step s >= 1: the peak levels are r_min, r_min + s,
     ... up to r_max, with one more level a step beyond each end, so level l has radius
     r_min - s + s l, l = 0 .. L - 1, L = floor((r_max - r_min) / s) + 3.  s = 1 is the plain
-    method."""
+    method.  READING: the lowest level keeps a radius of at least 1 (r_min - s >= 1), since
+    scores at different levels compare as S / r."""
+    if int(p["r_min"]) - int(p.get("r_step", 1)) < 1:
+        raise ValueError("the lowest level radius r_min - r_step must be at least 1")
     s = int(p.get("r_step", 1))
     L = (int(p["r_max"]) - int(p["r_min"])) // s + 3
     return int(p["r_min"]) - s + s * np.arange(L, dtype=np.int64)

@@ -30,6 +30,7 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
     FixedTables f;
     build_fixed_tables(p, f, budget);
     t.lbase = f.lbase;
+    t.rstep = f.rstep;
     t.L = f.L;
     t.wtab.assign(f.wtab, f.wtab + static_cast<size_t>(f.L) * (K_MAX + 1));
     t.ktab.assign(f.ktab, f.ktab + f.L);
@@ -43,11 +44,12 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
 namespace rd {
 
 void build_fixed_tables(const rd_params& p, FixedTables& t, size_t budget) {
-    t.lbase = p.r_min - 1;
-    t.L = p.r_max - p.r_min + 3;
+    t.rstep = param_rstep(p);
+    t.lbase = p.r_min - t.rstep;
+    t.L = (p.r_max - p.r_min) / t.rstep + 3;
     std::memset(t.wtab, 0, sizeof(t.wtab));
     for (int i = 0; i < t.L; ++i) {
-        const int l = t.lbase + i;
+        const int l = t.lbase + t.rstep * i;
         const double sg = level_sigma(p, l);
         const int K = level_radius(p, l);
         t.ktab[i] = K;
@@ -57,20 +59,21 @@ void build_fixed_tables(const rd_params& p, FixedTables& t, size_t budget) {
         t.thr[i] = static_cast<uint64_t>(
             std::floor(static_cast<double>(p.peak_fraction) * TWO_PI * static_cast<double>(l) * S_SCALE));
     }
-    // greedy level chunks: peak levels [rc0, rc1) need accumulator levels rc0-1 .. rc1
+    // greedy level chunks over the peak level indices 1 .. L - 2: peak levels [c0, c1) need
+    // accumulator levels c0 - 1 .. c1
     t.nchunks = 0;
     t.lds = 0;
-    int rc0 = p.r_min;
-    while (rc0 <= p.r_max) {
-        int rc1 = rc0 + 1;
-        while (rc1 <= p.r_max && rc1 + 1 - rc0 <= CHUNK_MAX &&
-               vote_lds_bytes(VOTE_TILE, rc1 + 1 - rc0 + 2, t.ktab[rc1 + 1 - t.lbase]) <= budget)
-            ++rc1;
-        t.chunks[t.nchunks++] = rc0;
-        t.lds = std::max(t.lds, vote_lds_bytes(VOTE_TILE, rc1 - rc0 + 2, t.ktab[rc1 - t.lbase]));
-        rc0 = rc1;
+    int c0 = 1;
+    while (c0 <= t.L - 2) {
+        int c1 = c0 + 1;
+        while (c1 <= t.L - 2 && c1 + 1 - c0 <= CHUNK_MAX &&
+               vote_lds_bytes(VOTE_TILE, c1 + 1 - c0 + 2, t.ktab[c1 + 1]) <= budget)
+            ++c1;
+        t.chunks[t.nchunks++] = c0;
+        t.lds = std::max(t.lds, vote_lds_bytes(VOTE_TILE, c1 - c0 + 2, t.ktab[c1]));
+        c0 = c1;
     }
-    t.chunks[t.nchunks] = p.r_max + 1;
+    t.chunks[t.nchunks] = t.L - 1;
 }
 
 StencilArgs stencil_args_for(const rd_params& p, const FrameDesc* frames, int nframes, int total_tiles) {
@@ -230,6 +233,7 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.rq = h->d_rq;
     a.bin_count = h->d_bin_count;
     a.lbase = h->tabs.lbase;
+    a.r_step = h->tabs.rstep;
     a.nlevels = h->tabs.L;
     a.vote_threshold = p.vote_threshold;
     a.chunk_start = h->d_chunks;
@@ -475,12 +479,17 @@ rd_status rd_validate_params(const rd_params* p) {
     if (!p) return RD_E_INVALID;
     if (!(p->sigma_smooth > 0.0f) || !(p->sigma_smooth <= 4.0f)) return RD_E_INVALID;
     if (!std::isfinite(p->k_threshold) || p->k_threshold > 0.0f) return RD_E_INVALID;
+    if (p->r_step < 0 || p->r_step > R_STEP_MAX) return RD_E_INVALID;
     if (p->r_min < 1 || p->r_max < p->r_min || p->r_max > R_LIMIT) return RD_E_INVALID;
+    const int rs = param_rstep(*p);
+    const int top = p->r_min + rs * ((p->r_max - p->r_min) / rs + 1);   // the level past r_max
+    // the lowest level's radius is at least 1: scores compare across levels as S / r
+    if (p->r_min - rs < 1 || top > R_LIMIT + 1) return RD_E_INVALID;
     if (p->vote_threshold < 0 || p->vote_threshold > 65535) return RD_E_INVALID;
     if (!std::isfinite(p->peak_fraction) || p->peak_fraction < 0.0f) return RD_E_INVALID;
     if (!std::isfinite(p->sig_slope) || !std::isfinite(p->sig_icpt)) return RD_E_INVALID;
     if (p->sig_slope < 0.0f || !(p->sig_icpt > 0.0f)) return RD_E_INVALID;
-    if (level_radius(*p, p->r_max + 1) > K_MAX) return RD_E_INVALID;
+    if (level_radius(*p, top) > K_MAX) return RD_E_INVALID;
     if (p->annulus_halfwidth < 0 || p->annulus_halfwidth > 64) return RD_E_INVALID;
     if (p->min_fit_points < 3) return RD_E_INVALID;
     if (p->measure != RD_MEASURE_RIDGE && p->measure != RD_MEASURE_EDGE) return RD_E_INVALID;

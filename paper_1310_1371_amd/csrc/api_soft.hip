@@ -145,6 +145,7 @@ rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess
     if (!h || !params || !acc_dev || n < 0 || (n > 0 && (!xy_dev || !hess_dev))) return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
+    if (param_rstep(*params) != 1) return RD_E_INVALID;             // levels in steps of one pixel
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;
@@ -193,6 +194,7 @@ rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hes
         return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
+    if (param_rstep(*params) != 1) return RD_E_INVALID;             // levels in steps of one pixel
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;

@@ -152,6 +152,7 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
     va.rq = d_rq;
     va.bin_count = d_bins;
     va.lbase = tabs.lbase;
+    va.r_step = tabs.rstep;
     va.nlevels = tabs.L;
     va.vote_threshold = params->vote_threshold;
     va.chunk_start = d_chunks;

@@ -21,9 +21,10 @@
 
 namespace rd {
 
-// Level tables for radii r_min - 1 .. r_max + 1 (index l - (r_min - 1)).
+// Level tables: level i has radius lbase + rstep i, i = 0 .. L - 1 (radii r_min - s .. past
+// r_max by one step); the chunk boundaries are level indices.
 struct LevelTables {
-    int lbase = 0, L = 0;
+    int lbase = 0, rstep = 1, L = 0;
     std::vector<uint32_t> wtab;      // L x (K_MAX + 1)
     std::vector<int32_t> ktab;       // L
     std::vector<uint64_t> thr;       // L
@@ -33,7 +34,7 @@ struct LevelTables {
 
 // The same tables in fixed-size arrays (no heap), for the entry point that allocates nothing.
 struct FixedTables {
-    int lbase = 0, L = 0, nchunks = 0;
+    int lbase = 0, rstep = 1, L = 0, nchunks = 0;
     uint32_t wtab[(R_LIMIT + 3) * (K_MAX + 1)];
     int32_t ktab[R_LIMIT + 3];
     uint64_t thr[R_LIMIT + 3];

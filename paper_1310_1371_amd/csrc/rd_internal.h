@@ -30,7 +30,11 @@ __host__ __device__ inline bool ridge_code_ok(int qx, int qy) {
 
 constexpr int RG_MAX = 16;   // Gaussian radius ceil(4 sigma) limit (sigma <= 4)
 constexpr int K_MAX = 24;    // smoothing window half-width limit
-constexpr int R_LIMIT = 126; // r_max limit: keeps u16 vote counts and u64 scores exact
+constexpr int R_LIMIT = 126; // largest level radius R_LIMIT + 1: keeps u16 vote counts and u64 scores exact
+constexpr int R_STEP_MAX = 16;
+
+// The radius step of a parameter set (0 reads as 1).
+inline int param_rstep(const rd_params& p) { return p.r_step < 1 ? 1 : p.r_step; }
 constexpr int MAX_DIM = 65535;
 
 // One frame of a launch: where its pixels are and where its tiles / bins start in the
@@ -79,10 +83,11 @@ struct VoteArgs {
     const uint32_t* rxy;
     const uint32_t* rq;
     const uint32_t* bin_count;
-    int32_t lbase;            // r_min - 1: level index 0
-    int32_t nlevels;          // r_max - r_min + 3
+    int32_t lbase;            // radius of level 0: r_min - r_step
+    int32_t r_step;           // level i has radius lbase + r_step i
+    int32_t nlevels;          // L = (r_max - r_min) / r_step + 3
     int32_t vote_threshold;
-    const int32_t* chunk_start;  // [nchunks + 1] peak-level boundaries
+    const int32_t* chunk_start;  // [nchunks + 1] peak-level boundaries (level indices)
     const uint32_t* wtab;        // [level][K_MAX + 1] 15-bit weight factors
     const int32_t* ktab;         // [level] window half-width
     const uint64_t* thr;         // [level] integer score threshold

@@ -147,8 +147,12 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         for (int i = tid; i < a.nframes; i += NT) sVt0[i] = a.frames[i].vtile0;
     __syncthreads();
 
-    const int lbase = a.lbase;
-    const int r_lo = sChunk[0], r_hi = sChunk[a.nchunks];     // peak levels [r_lo, r_hi)
+    // level i (0 .. L - 1) has radius rbase + rstep i; the chunk table holds level indices and
+    // the peak levels are 1 .. L - 2
+    const int rbase = a.lbase, rstep = a.r_step;
+    auto radius = [&](int i) { return rbase + rstep * i; };
+    const float inv_step = 1.0f / static_cast<float>(rstep);   // exact for rstep = 1
+    const int i_hi = sChunk[a.nchunks];                        // the top level, L - 1
     const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
     uint32_t st_votes = 0;                                              // statistics
     unsigned long long st_hot = 0, st_strong = 0, st_taps = 0;
@@ -178,11 +182,11 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         const int sy0 = max(y0 - 1, 0), sy1 = min(y0 + T + 1, H);
 
         // ---- candidate bins: every bin whose pixels can vote into the tile's widest
-        // accumulator region at some radius of r_lo - 1 .. r_hi
-        const int Km = sKt[r_hi - lbase];
+        // accumulator region at some level radius
+        const int Km = sKt[i_hi];
         const int ux0 = max(sx0 - Km, 0), ux1 = min(sx1 + Km, W);
         const int uy0 = max(sy0 - Km, 0), uy1 = min(sy1 + Km, H);
-        const int reach = r_hi + 1, far_lo = max(r_lo - 2, 0);
+        const int reach = radius(i_hi) + 1, far_lo = max(rbase - 1, 0);
         const int bxlo = max((ux0 - reach) >> BIN_SHIFT, 0), bxhi = min((ux1 - 1 + reach) >> BIN_SHIFT, fd.nbx - 1);
         const int bylo = max((uy0 - reach) >> BIN_SHIFT, 0), byhi = min((uy1 - 1 + reach) >> BIN_SHIFT, fd.nby - 1);
         const int nbxr = bxhi - bxlo + 1;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         auto prepare = [&](int c) {
             const int l0 = sChunk[c] - 1, l1 = sChunk[c + 1];
             const int nlev = l1 - l0 + 1;
-            const int Kc = sKt[l1 - lbase];
+            const int Kc = sKt[l1];
             const int AW = min(sx1 + Kc, W) - max(sx0 - Kc, 0), AH = min(sy1 + Kc, H) - max(sy0 - Kc, 0);
             const int words = (nlev * ((AW + 8) & ~7) * AH) >> 1;
             uint4* a4 = reinterpret_cast<uint4*>(sA);
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
             for (int i = tid; i < nlev * NWW; i += NT) {
                 const int li = i / NWW, j = i - li * NWW;
-                const int lg = l0 + li - lbase, K = sKt[lg];
+                const int lg = l0 + li, K = sKt[lg];
                 uint32_t wl[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -244,9 +248,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
 
         for (int c = 0; c < a.nchunks; ++c) {
             const int rc0 = sChunk[c], rc1 = sChunk[c + 1];
-            const int l0 = rc0 - 1, l1 = rc1;                // accumulator levels, inclusive
+            const int l0 = rc0 - 1, l1 = rc1;                // accumulator level indices, inclusive
             const int nlev = l1 - l0 + 1;
-            const int Kc = sKt[l1 - lbase];                   // widest window of the chunk
+            const int Kc = sKt[l1];                           // widest window of the chunk
             const int ax0 = max(sx0 - Kc, 0), ax1 = min(sx1 + Kc, W);
             const int ay0 = max(sy0 - Kc, 0), ay1 = min(sy1 + Kc, H);
             const int AW = ax1 - ax0, AH = ay1 - ay0;
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             const int64_t slot = (fd.bin0 + sBinId[lo]) * BIN_CAP + (g - sBinPre[lo]);
                             xy = a.rxy[slot];
                             q = a.rq[slot];
-                            // levels (relative to lbase) at which each sign's vote can land in the
+                            // levels (indices) at which each sign's vote can land in the
                             // tile's widest accumulator region: |rho - l q / 2^14| <= 1/2 per axis
                             const int x = xy & 0xffffu, y = xy >> 16;
                             const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
@@ -285,7 +289,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
 #pragma unroll
                             for (int sg = 0; sg < 2; ++sg) {
                                 const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
-                                float lo_l = static_cast<float>(r_lo - 1), hi_l = static_cast<float>(r_hi);
+                                // radii first, then level indices with one level of margin
+                                float lo_l = static_cast<float>(rbase), hi_l = static_cast<float>(radius(i_hi));
                                 bool ok = true;
                                 if (sqx != 0) {
                                     const float inv = 16384.0f * __builtin_amdgcn_rcpf(static_cast<float>(sqx));
@@ -308,9 +313,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                                     ok = ok && y >= uy0 && y < uy1;
                                 }
                                 int la = 255, lb = 0;                      // empty
-                                if (ok && lo_l <= hi_l + 2.0f) {
-                                    la = max(r_lo - 1, static_cast<int>(floorf(lo_l)) - 1) - lbase;
-                                    lb = min(r_hi, static_cast<int>(ceilf(hi_l)) + 1) - lbase;
+                                if (ok && lo_l <= hi_l + 2.0f * static_cast<float>(rstep)) {
+                                    la = max(0, static_cast<int>(floorf((lo_l - static_cast<float>(rbase)) * inv_step)) - 1);
+                                    lb = min(i_hi, static_cast<int>(ceilf((hi_l - static_cast<float>(rbase)) * inv_step)) + 1);
                                     if (lb < la) { la = 255; lb = 0; }
                                 }
                                 rr |= (static_cast<uint32_t>(la) | (static_cast<uint32_t>(lb) << 8)) << (16 * sg);
@@ -380,22 +385,23 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int it = sOrd[k >> 1];
                     const int jr = it >> 1, sg = it & 1;
                     const uint32_t rr = sRidR[jr] >> (16 * sg);
-                    const int la_raw = static_cast<int>(rr & 0xffu) + lbase;
+                    const int la_raw = static_cast<int>(rr & 0xffu);
                     if (la_raw > l1) break;                       // the rest start later still
-                    const int la0 = max(la_raw, l0), lb0 = min(static_cast<int>((rr >> 8) & 0xffu) + lbase, l1);
+                    const int la0 = max(la_raw, l0), lb0 = min(static_cast<int>((rr >> 8) & 0xffu), l1);
                     const int mid = (la0 + lb0) >> 1;
                     const int la = (k & 1) ? mid + 1 : la0, lb = (k & 1) ? lb0 : mid;
                     if (la > lb) continue;
                     const uint32_t xy = sRidXY[jr], q = sRidQ[jr];
                     const int x = (xy & 0xffffu) - ax0, y = (xy >> 16) - ay0;
                     const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
-                    // fixed-point offsets, advanced by q per level.  The mirrored vote is
-                    // x - floor((l q + 2^13) / 2^14) (not x + rho(l, -q): they differ at exact
-                    // halves), which equals x + floor((-l q + 2^13 - 1) / 2^14), so both signs
+                    // fixed-point offsets, advanced by rstep q per level.  The mirrored vote is
+                    // x - floor((r q + 2^13) / 2^14) (not x + rho(r, -q): they differ at exact
+                    // halves), which equals x + floor((-r q + 2^13 - 1) / 2^14), so both signs
                     // take the same form with a signed step and rounding constant
                     const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy;
                     const int rnd = sg ? 8191 : 8192;
-                    int accx = la * sqx + rnd, accy = la * sqy + rnd;
+                    int accx = radius(la) * sqx + rnd, accy = radius(la) * sqy + rnd;
+                    const int stx = rstep * sqx, sty = rstep * sqy;
                     // byte offsets of the u16 counters: 2 u within a row, row stride 2 AWP
                     const int x2 = 2 * x, AW2 = 2 * AW, AWP2 = 2 * AWP;
                     int base = 2 * (la - l0) * plane;
@@ -431,8 +437,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                                          static_cast<uint32_t>((v - hv0 + sy0 - (y0 - 1)) * SR + (u - hu0 + sx0 - (x0 - 1)));
                             }
                         }
-                        accx += sqx;
-                        accy += sqy;
+                        accx += stx;
+                        accy += sty;
                         base += 2 * plane;
                     }
                     if (pend_h < static_cast<uint32_t>(HCAP)) {
@@ -452,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 for (int li = 0; li < nlev; ++li)
                     for (int i = tid; i < iw * ih; i += NT) {
                         const int y = y0 + i / iw, x = x0 + i % iw;
-                        a.acc_dump[((int64_t)(l0 + li - lbase) * H + y) * W + x] =
+                        a.acc_dump[((int64_t)(l0 + li) * H + y) * W + x] =
                             get_u16(sA, li * plane + (y - ay0) * AWP + (x - ax0));
                     }
             }
@@ -500,7 +506,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             const int li = e >> 16;
                             if (li < wlo - 1 || li > whi) continue;
                             const unsigned long long sc = sHS[h];
-                            if (sc > sThr[l0 + li - lbase]) {
+                            if (sc > sThr[l0 + li]) {
                                 const uint32_t j = atomicAdd(&sNs, 1u);
                                 if (j < static_cast<uint32_t>(SCAP)) {
                                     sStrongS[j] = sc;
@@ -541,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int sub = task - h * ntk, bi = sub >> 1, half = sub & 1;
                     const uint32_t e = sHot[h];
                     const int li = e >> 16, sidx = e & 0xffff;
-                    const int lg = l0 + li - lbase;
+                    const int lg = l0 + li;
                     const int K = sKt[lg];
                     const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
                     const int cs = max(vx - K, ax0) - ax0, ce = min(vx + K, ax1 - 1) - ax0;
@@ -598,9 +604,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     if (DUMP && first && a.score_dump) {
                         const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
                         if (vx >= x0 && vx < x0 + T && vy >= y0 && vy < y0 + T)
-                            a.score_dump[((int64_t)(l0 + li - lbase) * H + vy) * W + vx] = sc;
+                            a.score_dump[((int64_t)(l0 + li) * H + vy) * W + vx] = sc;
                     }
-                    if (sc > sThr[l0 + li - lbase]) {
+                    if (sc > sThr[l0 + li]) {
                         if (first) atomicAdd(&sLevN[li], 1u);
                         const uint32_t j = atomicAdd(&sNs, 1u);
                         if (j < static_cast<uint32_t>(SCAP)) {
@@ -638,15 +644,15 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const uint32_t idx = atomicAdd(&a.peak_count[f], 1u);
                     if (idx < static_cast<uint32_t>(a.max_peaks)) {
                         Peak pk;
-                        pk.a = x0 - 1 + sxr; pk.b = y0 - 1 + syr; pk.r = lm; pk.frame = f; pk.s = sStrongS[j];
+                        pk.a = x0 - 1 + sxr; pk.b = y0 - 1 + syr; pk.r = radius(lm); pk.frame = f; pk.s = sStrongS[j];
                         a.peaks[fd.peak0 + idx] = pk;
                     }
                 };
                 // a neighbour beats v if its S_int / r is larger, or equal and it comes before v in
                 // (r, y, x) order; a neighbour below the threshold cannot, so only strong ones count
                 auto beats = [&](unsigned long long sv, int lm, int k, int dl, int dy, int dx) {
-                    const unsigned long long lhs = sv * static_cast<unsigned long long>(lm + dl);
-                    const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(lm);
+                    const unsigned long long lhs = sv * static_cast<unsigned long long>(radius(lm + dl));
+                    const unsigned long long rhs = sStrongS[k] * static_cast<unsigned long long>(radius(lm));
                     const bool earlier = dl < 0 || (dl == 0 && (dy < 0 || (dy == 0 && dx < 0)));
                     return earlier ? !(lhs > rhs) : !(lhs >= rhs);
                 };

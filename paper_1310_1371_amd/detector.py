@@ -213,7 +213,7 @@ class Detector:
         """Dense vote accumulator (int32 view of uint32, [L, H, W]) and integer scores (int64 view of
         uint64, [L, H, W]) from a given ridge list."""
         xy, q = self._ridge_tensors(xy, q)
-        L = int(params["r_max"]) - int(params["r_min"]) + 3
+        L = N.n_levels(params)
         dev = f"cuda:{self.device}"
         acc = torch.empty((L, height, width), dtype=torch.int32, device=dev)
         sc = torch.empty((L, height, width), dtype=torch.int64, device=dev) if scores else None

@@ -24,7 +24,7 @@ class RdParams(ctypes.Structure):
                 ("vote_threshold", ctypes.c_int32), ("peak_fraction", ctypes.c_float),
                 ("sig_slope", ctypes.c_float), ("sig_icpt", ctypes.c_float),
                 ("annulus_halfwidth", ctypes.c_int32), ("min_fit_points", ctypes.c_int32),
-                ("measure", ctypes.c_int32)]
+                ("measure", ctypes.c_int32), ("r_step", ctypes.c_int32)]
 
 
 class RdRing(ctypes.Structure):
@@ -132,4 +132,10 @@ def make_params(d: dict) -> RdParams:
     return RdParams(float(d["sigma_smooth"]), float(d["k_threshold"]), int(d["r_min"]), int(d["r_max"]),
                     int(d["vote_threshold"]), float(d["peak_fraction"]), float(d["sig_slope"]),
                     float(d["sig_icpt"]), int(d["annulus_halfwidth"]), int(d["min_fit_points"]),
-                    int(d.get("measure", 0)))
+                    int(d.get("measure", 0)), int(d.get("r_step", 1)))
+
+
+def n_levels(d: dict) -> int:
+    """Accumulator levels of a parameter set: (r_max - r_min) / r_step + 3."""
+    s = max(int(d.get("r_step", 1)), 1)
+    return (int(d["r_max"]) - int(d["r_min"])) // s + 3

@@ -58,6 +58,10 @@ def _p(**kw):
     (dict(peak_fraction=-0.1), False), (dict(sig_slope=-0.01), False), (dict(sig_icpt=0.0), False),
     (dict(sig_slope=0.2, r_max=126), False),
     (dict(annulus_halfwidth=-1), False), (dict(min_fit_points=2), False),
+    (dict(r_step=0), True), (dict(r_step=3), True), (dict(r_step=-1), False), (dict(r_step=17), False),
+    (dict(r_min=4, r_step=4), False), (dict(r_min=5, r_step=4), True), (dict(r_min=1), False),
+    (dict(r_min=2), True),
+    (dict(r_min=100, r_max=124, r_step=3), True), (dict(r_min=100, r_max=124, r_step=4), False),
 ])
 def test_validate_params(kw, ok):
     lib = _ensure_built()
@@ -66,18 +70,21 @@ def test_validate_params(kw, ok):
 
 
 @pytest.mark.parametrize("params", [synth.PARAMS_C1, synth.PARAMS_C2, synth.PARAMS_C5,
-                                    dict(O.DEFAULTS, sig_slope=0.07, sig_icpt=0.4, peak_fraction=0.33)])
+                                    dict(O.DEFAULTS, sig_slope=0.07, sig_icpt=0.4, peak_fraction=0.33),
+                                    dict(synth.PARAMS_C2, r_step=3), dict(synth.PARAMS_C5, r_step=2)])
 def test_level_tables_match_oracle(params):
     lib = _ensure_built()
     p = dict(O.DEFAULTS, **params)
-    L = p["r_max"] - p["r_min"] + 3
+    L = N.n_levels(p)
     k = np.zeros(L, np.int32)
     w = np.zeros(L * 25, np.uint32)
     t = np.zeros(L, np.uint64)
     st = lib.rd_level_tables(ctypes.byref(N.make_params(p)), L, k.ctypes.data, w.ctypes.data, t.ctypes.data)
     assert st == N.RD_OK
+    radii = O.level_radii(p)
+    assert len(radii) == L
     for i in range(L):
-        r = p["r_min"] - 1 + i
+        r = int(radii[i])
         assert k[i] == O.level_radius(r, p)
         wf = O.weight_factors(r, p)
         np.testing.assert_array_equal(w[i * 25:i * 25 + len(wf)], wf)
