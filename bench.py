@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--diff-frames", type=int, default=16, help="frames of the differentiable step (0: skip)")
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--stream-frames", type=int, default=2000, help="frames of the stream, 32 per launch (0: skip)")
+    ap.add_argument("--coded-launches", type=int, default=4,
+                    help="32-frame calls of the stream through encoded ridge streams (0: skip)")
     ap.add_argument("--cpu-frames", type=int, default=8, help="frames of the single-process oracle sample")
     ap.add_argument("--cpu-pool-frames", type=int, default=32, help="frames of the frame-parallel oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -648,16 +650,56 @@ def stream(det, args, np, torch, synth):
     dt = time.perf_counter() - t0
     tracks = linker.info()["tracks"]
     linker.close()
+    coded = ridge_streams(det, frames, p, np, torch, args.coded_launches) if args.coded_launches > 0 else None
     del store, frames
     truth = np.stack([xs, ys, st.radius(zs)], 2)
     acc = link_accuracy(np, linked, truth, np.sqrt((st.radius(zs) - 8.0) / 72.0))
     return {"frames": n, "launches_timed": len(launches), "frames_per_s": n / dt,
             "value": n * st.W * st.H / dt / 1e6, "unit": "Mpixel/s", "ms_per_launch": dt / len(launches) * 1e3,
             "s_total": dt, "rings_detected_and_refined": n_rings, "tracks": tracks, "linking": acc,
-            "s_render_untimed": t_render,
+            "s_render_untimed": t_render, "encoded_ridge_streams": coded,
             "workload": f"the whole {n}-frame 2048^2 u16 stream (1000 rings on random walks, radii 8-80), rendered "
                         f"on the GPU and resident in HBM, {len(launches)} launches of up to 32 frames, each: "
                         "batched detection, 20 LM steps per detection, linking (gate 8 px, memory 2) and depth"}
+
+
+def ridge_streams(det, frames, p, np, torch, launches=4):
+    """The stream's frames as encoded ridge streams, 32 frames per call: steps 1-2 and the
+    encoding on the GPU (rd_encode_ridges), the streams copied to pinned host memory (the
+    transfer the format is for), then steps 3-5 from the host copy (rd_detect_encoded, which
+    stages it back).  The rings must equal rd_detect_batch's on the same frames."""
+    n = min(launches * 32, frames.shape[0])
+    batches = [[frames[i] for i in range(k, min(k + 32, n))] for k in range(0, n, 32)]
+    buf = torch.empty(32 * 2 * 2048 * 2048 // 4, dtype=torch.uint8, device="cuda")
+    pinned = torch.empty(buf.numel(), dtype=torch.uint8).pin_memory()
+    host = pinned.numpy()
+    enc, offs = det.encode_ridges(batches[0], p, out=buf)           # warm-up
+    same = all(a.tobytes() == b.tobytes() for a, b in
+               zip(det.detect_encoded(enc, offs, p), det.detect_batch(batches[0], p)))
+    t_enc = t_copy = t_det = 0.0
+    nbytes = 0
+    for fb in batches:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        enc, offs = det.encode_ridges(fb, p, out=buf)
+        t1 = time.perf_counter()
+        total = int(offs[-1])
+        pinned[:total].copy_(enc[:total])
+        t2 = time.perf_counter()
+        det.detect_encoded(host[:total], offs, p)
+        t3 = time.perf_counter()
+        t_enc += t1 - t0
+        t_copy += t2 - t1
+        t_det += t3 - t2
+        nbytes += total
+    nf = sum(len(b) for b in batches)
+    raw = 2 * 2048 * 2048
+    return {"frames": nf, "bytes_per_frame": nbytes / nf, "raw_bytes_per_frame": raw,
+            "compression": raw * nf / nbytes, "rings_equal_rd_detect_batch": bool(same),
+            "encode_frames_per_s": nf / t_enc, "copy_to_host_GBs": nbytes / t_copy / 1e9,
+            "detect_from_host_streams_frames_per_s": nf / t_det,
+            "workload": f"{nf} frames of the 2048^2 stream, 32 per call: rd_encode_ridges on the resident frames, "
+                        "the streams copied to pinned host memory, rd_detect_encoded from that copy"}
 
 
 def link_accuracy(np, linked, truth, z_truth):

@@ -260,6 +260,42 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
                            int64_t n, int32_t width, int32_t height, const rd_params* params,
                            rd_ring* out, int32_t capacity, int32_t* n_rings);
 
+/* ---- encoded ridge streams ----------------------------------------------------------------
+ *
+ * A frame's ridges (pixel and direction code) in a compact, self-describing byte stream that
+ * stands in for the frame after step 2 (SI, "Additional notes": the ridge coordinates with
+ * their directions as a compressed representation of the image; Introduction: the data
+ * flow of the experiment is about 180 GB per hour).  Stream of one frame, little endian:
+ *   bytes 0-15   u32 0x31524452 ("RDR1"), u16 width, u16 height, u32 ridge count n, u32 0
+ *   then         u16 per 16x16 pixel bin (bins in raster order): ridges in the bin
+ *   then         u8 per ridge, the ridges bin after bin: its pixel in the bin, (y & 15) << 4 | (x & 15)
+ *   then         zero bytes to a multiple of 4, then u32 per ridge in the same order:
+ *                qx | qy << 16 (the direction code of step 1), then zero bytes to a multiple of 16
+ * About 5 bytes per ridge plus 2 per 256 pixels (a 2048^2 u16 frame of the stream workload:
+ * about 1 MB against 8 MB).  Streams of a batch follow each other, each 16-byte aligned. */
+
+/* Steps 1-2 on n frames (as rd_detect_batch takes them), then their ridges encoded into
+ * out_dev (a 16-byte aligned device buffer of `capacity` bytes), frame i at byte offsets[i]
+ * (host array of n + 1; offsets[n] = the total).  The ridges are those rd_detect finds.
+ * RD_E_TRUNCATED if the total exceeds capacity: the offsets are still filled, and the
+ * frames that do not fit are not written. */
+rd_status rd_encode_ridges(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params,
+                           uint8_t* out_dev, int64_t capacity, int64_t* offsets);
+
+/* Steps 3-5 from n encoded streams: stream i at enc + offsets[i] (offsets: host array of
+ * n + 1; each stream 16-byte aligned relative to offsets[0], and offsets[i + 1] - offsets[i]
+ * at least its size), enc in host memory (on_device = 0, copied in) or device memory
+ * (on_device = 1).  Every stream is checked: the header (magic, width and height 32 ..
+ * the context's maxima, n <= width * height, the stream long enough) on the host, then on the
+ * device the bin counts (each <= 256, summing to n) and every ridge: inside the frame, a
+ * direction code step 1 produces (as rd_validate_ridges) and its pixel listed once;
+ * RD_E_INVALID on any failure, before the votes.  Output as rd_detect_batch (rings of frame
+ * i at out + out_offsets[i], at most capacities[i], n_rings[i] the count).  The rings are
+ * those rd_detect_batch finds on the frames the streams were encoded from. */
+rd_status rd_detect_encoded(rd_handle h, const uint8_t* enc, int32_t on_device, const int64_t* offsets, int32_t n,
+                            const rd_params* params, rd_ring* out, const int64_t* out_offsets,
+                            const int32_t* capacities, int32_t* n_rings);
+
 /* ---- detection without allocation ------------------------------------------------------
  *
  * For callers that cannot allocate device memory (tight serving loops, harnesses that forbid

@@ -452,6 +452,40 @@ rd_status check_batch(rd_ctx* h, const rd_frame* frames, int32_t n) {
     return RD_OK;
 }
 
+// Chunk numbering of a launch's frames for the ridge-stream kernels (h_frames filled):
+// chunk0[i] = first chunk of frame i, chunk0[n] = total; uploaded next to the frame counts.
+rd_status upload_chunks(rd_ctx* h, int n, int* total_chunks) {
+    std::vector<uint32_t> c0(n + 1);
+    int64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        c0[i] = static_cast<uint32_t>(tot);
+        tot += (static_cast<int64_t>(h->h_frames[i].nbx) * h->h_frames[i].nby + RIDGE_CHUNK - 1) / RIDGE_CHUNK;
+    }
+    c0[n] = static_cast<uint32_t>(tot);
+    if (tot > h->max_chunks) return RD_E_TOO_LARGE;
+    RD_HIP(hipMemcpyAsync(h->d_cmeta + h->max_frames, c0.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));        // c0 is a local vector
+    *total_chunks = static_cast<int>(tot);
+    return RD_OK;
+}
+
+RidgeCodeArgs ridge_code_args(rd_ctx* h, int n) {
+    RidgeCodeArgs a{};
+    a.frames = h->d_frames;
+    a.nframes = n;
+    a.chunk0 = h->d_cmeta + h->max_frames;
+    a.cbase = h->d_cbase;
+    a.frame_n = h->d_cmeta;
+    a.flags = h->d_cmeta + 2 * h->max_frames + 2;
+    a.rxy = h->d_rxy;
+    a.rq = h->d_rq;
+    a.rk = h->d_rk;
+    a.bin_count = h->d_bin_count;
+    a.offsets = h->d_eoff;
+    return a;
+}
+
 bool valid_tuning(const rd_tuning& t) {
     return t.stencil_tile >= 0 && t.stencil_tile < STENCIL_VARIANTS && t.vote_lds_kb >= 16 &&
            t.vote_lds_kb * 1024 <= VOTE_LDS_MAX && (t.use_graph == 0 || t.use_graph == 1);
@@ -576,6 +610,10 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_chunks), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_offsets), bins_single * sizeof(int64_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_pixmask), bins_single * 8 * sizeof(uint32_t)) == hipSuccess;
+    h->max_chunks = h->max_bins / RIDGE_CHUNK + h->max_frames + 1;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_cbase), h->max_chunks * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_cmeta), (2 * h->max_frames + 4) * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_eoff), (h->max_frames + 1) * sizeof(int64_t)) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_rings), npk * sizeof(rd_ring), hipHostMallocMapped) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t),
                              hipHostMallocMapped) == hipSuccess;
@@ -616,6 +654,9 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_chunks);
     (void)hipFree(h->d_offsets);
     (void)hipFree(h->d_pixmask);
+    (void)hipFree(h->d_cbase);
+    (void)hipFree(h->d_cmeta);
+    (void)hipFree(h->d_eoff);
     for (hipEvent_t& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_rings) (void)hipHostFree(h->h_rings);
@@ -814,6 +855,125 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
     record_stats(h, 1);
     if (h->h_counts[1]) return RD_E_OVERFLOW;
     return copy_rings(h, 0, out, capacity, n_rings);
+}
+
+rd_status rd_encode_ridges(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params, uint8_t* out_dev,
+                           int64_t capacity, int64_t* offsets) {
+    if (!h || !params || !offsets || capacity < 0 || (capacity > 0 && !out_dev)) return RD_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(out_dev) % 16 != 0) return RD_E_INVALID;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_batch(h, frames, n));
+    RD_HIP(hipSetDevice(h->device));
+    const int rg = gauss_radius(params->sigma_smooth);
+    int tt = 0, tv = 0;
+    RD_TRY(setup_frames(h, frames, n, rg, h->tune.stencil_tile, false, &tt, &tv));
+    int chunks = 0;
+    RD_TRY(upload_chunks(h, n, &chunks));
+    StencilArgs sa = stencil_args(h, *params, n, tt);
+    sa.ridge_total = nullptr;
+    RD_HIP(launch_stencil(sa, frames[0].dtype, rg, h->tune.stencil_tile, false, h->stream));
+    RidgeCodeArgs a = ridge_code_args(h, n);
+    a.enc = out_dev;
+    a.capacity = capacity;
+    RD_HIP(launch_ridge_encode(a, chunks, h->stream));
+    RD_HIP(hipMemcpyAsync(offsets, h->d_eoff, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    return offsets[n] > capacity ? RD_E_TRUNCATED : RD_OK;
+}
+
+rd_status rd_detect_encoded(rd_handle h, const uint8_t* enc, int32_t on_device, const int64_t* offsets, int32_t n,
+                            const rd_params* params, rd_ring* out, const int64_t* out_offsets,
+                            const int32_t* capacities, int32_t* n_rings) {
+    if (!h || !enc || !offsets || !params || !out_offsets || !capacities || !n_rings) return RD_E_INVALID;
+    if (on_device != 0 && on_device != 1) return RD_E_INVALID;
+    RD_TRY(rd_validate_params(params));
+    if (n < 1) return RD_E_INVALID;
+    if (n > h->max_frames) return RD_E_TOO_LARGE;
+    for (int i = 0; i < n; ++i) {
+        n_rings[i] = 0;
+        if (capacities[i] < 0 || (capacities[i] > 0 && !out) || out_offsets[i] < 0) return RD_E_INVALID;
+    }
+    RD_HIP(hipSetDevice(h->device));
+    // the headers, checked on the host: magic, size, the stream long enough for its count
+    std::vector<uint32_t> hdr(4 * static_cast<size_t>(n));
+    for (int i = 0; i < n; ++i) {
+        if (offsets[i] < 0 || offsets[i + 1] < offsets[i] || (offsets[i] - offsets[0]) % 16 != 0) return RD_E_INVALID;
+        if (on_device) {
+            if (reinterpret_cast<uintptr_t>(enc + offsets[i]) % 16 != 0) return RD_E_INVALID;
+            if (offsets[i + 1] - offsets[i] < 16) return RD_E_INVALID;
+            RD_HIP(hipMemcpyAsync(&hdr[4 * i], enc + offsets[i], 16, hipMemcpyDeviceToHost, h->stream));
+        } else {
+            if (offsets[i + 1] - offsets[i] < 16) return RD_E_INVALID;
+            std::memcpy(&hdr[4 * i], enc + offsets[i], 16);
+        }
+    }
+    if (on_device) RD_HIP(hipStreamSynchronize(h->stream));
+    int64_t px = 0, bins = 0;
+    int tv = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint32_t* hd = &hdr[4 * i];
+        const int W = static_cast<int>(hd[1] & 0xffffu), H = static_cast<int>(hd[1] >> 16);
+        if (hd[0] != RIDGE_MAGIC || hd[3] != 0u || W < 32 || H < 32) return RD_E_INVALID;
+        if (W > h->max_w || H > h->max_h) return RD_E_TOO_LARGE;
+        FrameDesc fd{};
+        fd.W = W;
+        fd.H = H;
+        fd.nbx = (W + BIN - 1) / BIN;
+        fd.nby = (H + BIN - 1) / BIN;
+        const int64_t nb = static_cast<int64_t>(fd.nbx) * fd.nby;
+        if (static_cast<int64_t>(hd[2]) > static_cast<int64_t>(W) * H) return RD_E_INVALID;
+        if (offsets[i + 1] - offsets[i] < ridge_stream_bytes(hd[2], nb)) return RD_E_INVALID;
+        fd.vtile0 = tv;
+        fd.bin0 = bins;
+        fd.peak0 = i * h->max_peaks;
+        h->h_frames[i] = fd;
+        tv += vote_tiles(W, H);
+        bins += nb;
+        px += static_cast<int64_t>(W) * H;
+    }
+    if (px > h->max_batch_px || bins > h->max_bins) return RD_E_TOO_LARGE;
+    RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, n * sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
+    h->frames_dev_n = 0;                               // not a descriptor set setup_frames knows
+    // the streams on the device: in place, or staged in one copy
+    const uint8_t* dev = enc;
+    std::vector<int64_t> doff(n + 1);
+    for (int i = 0; i <= n; ++i) doff[i] = on_device ? offsets[i] : offsets[i] - offsets[0];
+    if (!on_device) {
+        const int64_t bytes = offsets[n] - offsets[0];
+        if (bytes > h->max_batch_px * 4 + static_cast<int64_t>(h->max_frames) * 256) return RD_E_TOO_LARGE;
+        RD_HIP(hipMemcpyAsync(h->d_stage, enc + offsets[0], bytes, hipMemcpyHostToDevice, h->stream));
+        dev = static_cast<const uint8_t*>(h->d_stage);
+    }
+    RD_HIP(hipMemcpyAsync(h->d_eoff, doff.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+    int chunks = 0;
+    RD_TRY(upload_chunks(h, n, &chunks));              // synchronises: doff is uploaded by then
+    RD_TRY(upload_tables(h, *params));
+    RidgeCodeArgs a = ridge_code_args(h, n);
+    a.enc = const_cast<uint8_t*>(dev);
+    RD_HIP(launch_zero(a.flags, 1, h->stream));
+    RD_HIP(launch_ridge_decode(a, chunks, h->stream));
+    uint32_t flag = 0;
+    RD_HIP(hipMemcpyAsync(&flag, a.flags, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    if (flag) return RD_E_INVALID;
+    h->mark_now = h->timing;
+    const rd_status st = enqueue(h, *params, n, RD_F32, 0, false, 0, tv, h->dh_rings, h->dh_counts);
+    if (st != RD_OK) {
+        h->mark_now = false;
+        return st;
+    }
+    RD_HIP(hipStreamSynchronize(h->stream));
+    collect_timing(h, false);
+    h->mark_now = false;
+    record_stats(h, n);
+    if (h->h_counts[n]) return RD_E_OVERFLOW;
+    rd_status result = RD_OK;
+    for (int i = 0; i < n; ++i) {
+        const rd_status r = copy_rings(h, i, out ? out + out_offsets[i] : nullptr, capacities[i], &n_rings[i]);
+        if (r == RD_E_OVERFLOW) return r;
+        if (r != RD_OK) result = r;
+    }
+    return result;
 }
 
 }  // extern "C"

@@ -96,6 +96,12 @@ struct rd_ctx {
     int32_t* d_chunks = nullptr;
     int64_t* d_offsets = nullptr;       // stage gather offsets (per bin of one frame)
     uint32_t* d_pixmask = nullptr;      // caller ridge lists: one bit per pixel of one frame's bins
+    // encoded ridge streams: per-chunk record bases (256 bins a chunk), per-frame ridge counts,
+    // first chunk of each frame and an error flag (d_cmeta), stream byte offsets (d_eoff)
+    uint32_t* d_cbase = nullptr;
+    uint32_t* d_cmeta = nullptr;
+    int64_t* d_eoff = nullptr;
+    int64_t max_chunks = 0;
     // pinned host memory; rings and counts are written by the fit kernel through mappings
     rd_ring* h_rings = nullptr;
     rd_ring* dh_rings = nullptr;

@@ -119,6 +119,39 @@ struct FitArgs {
     int32_t nstats;
 };
 
+// ---- encoded ridge streams (the compact transfer form of a frame's ridges)
+constexpr int RIDGE_CHUNK = 256;          // bins per work unit of the encode / decode kernels
+constexpr uint32_t RIDGE_MAGIC = 0x31524452u;   // "RDR1"
+// byte size of one frame's stream: header, u16 per bin, u8 per ridge, pad to 4, u32 per ridge,
+// pad to 16
+__host__ __device__ inline int64_t ridge_stream_bytes(int64_t n, int64_t nbins) {
+    const int64_t qoff = (16 + 2 * nbins + n + 3) & ~static_cast<int64_t>(3);
+    return (qoff + 4 * n + 15) & ~static_cast<int64_t>(15);
+}
+__host__ __device__ inline int64_t ridge_stream_qoff(int64_t n, int64_t nbins) {
+    return (16 + 2 * nbins + n + 3) & ~static_cast<int64_t>(3);
+}
+
+struct RidgeCodeArgs {
+    const FrameDesc* frames;
+    int32_t nframes;
+    const uint32_t* chunk0;      // [nframes + 1] first chunk of each frame (launch-wide numbering)
+    uint32_t* cbase;             // [chunks] record index of each chunk's first ridge in its frame
+    uint32_t* frame_n;           // [nframes] ridges per frame
+    uint32_t* flags;             // decode: bit 0 malformed stream (counts, size), bit 1 off-frame
+                                 // pixel, bit 2 bad direction code, bit 3 repeated pixel
+    uint32_t* rxy;               // the context's ridge bins
+    uint32_t* rq;
+    float* rk;
+    uint32_t* bin_count;
+    uint8_t* enc;                // encode: output buffer; decode: staged streams
+    int64_t capacity;            // encode: bytes of enc
+    int64_t* offsets;            // [nframes + 1] stream byte offsets (encode: written; decode: read)
+};
+
+hipError_t launch_ridge_encode(const RidgeCodeArgs& a, int total_chunks, hipStream_t s);
+hipError_t launch_ridge_decode(const RidgeCodeArgs& a, int total_chunks, hipStream_t s);
+
 // flags of a caller-given ridge list (BinArgs::flags)
 enum { BIN_OVERFLOW = 1, BIN_OFF_FRAME = 2, BIN_BAD_CODE = 4, BIN_DUPLICATE = 8 };
 

@@ -142,6 +142,49 @@ class Detector:
         raw = buf.view(np.uint8)
         return [_copy_rings(raw, i * cap, counts[i]) for i in range(n)]
 
+    # -------------------------------------------------------------------- encoded ridge streams
+    def encode_ridges(self, frames, params: dict, out: torch.Tensor | None = None):
+        """Steps 1-2 on a list of frames, their ridges as encoded streams: (uint8 CUDA tensor
+        holding the streams, int64 numpy offsets of n + 1).  `out` (uint8 CUDA tensor) is reused
+        when it is large enough."""
+        n = len(frames)
+        arr = self._frame_array(frames)
+        p = N.make_params(params)
+        offs = np.zeros(n + 1, dtype=np.int64)
+        if out is None:
+            px = sum(int(f.shape[0]) * int(f.shape[1]) for f in frames)
+            out = torch.empty(px + 64 * n + 1024, dtype=torch.uint8, device=self._dev())
+        po = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st = self._lib.rd_encode_ridges(self._h, arr, n, ctypes.byref(p), out.data_ptr(), out.numel(), po)
+        if st == N.RD_E_TRUNCATED:
+            out = torch.empty(int(offs[n]), dtype=torch.uint8, device=self._dev())
+            st = self._lib.rd_encode_ridges(self._h, arr, n, ctypes.byref(p), out.data_ptr(), out.numel(), po)
+        N.check(st, "rd_encode_ridges")
+        return out, offs
+
+    def detect_encoded(self, enc, offsets, params: dict, capacity_per_frame: int | None = None) -> list:
+        """Rings of every encoded stream (a uint8 numpy array in host memory or a uint8 CUDA
+        tensor, with its n + 1 offsets).  Returns a list of RING_DTYPE arrays."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        n = len(offsets) - 1
+        if isinstance(enc, torch.Tensor):
+            on_dev, ptr = (1 if enc.is_cuda else 0), enc.data_ptr()
+        else:
+            enc = np.ascontiguousarray(enc, dtype=np.uint8)
+            on_dev, ptr = 0, enc.ctypes.data
+        cap = capacity_per_frame or self.max_peaks
+        buf = np.empty(n * cap, dtype=RING_DTYPE)
+        out = ctypes.cast(buf.ctypes.data, ctypes.POINTER(N.RdRing))
+        oo = (ctypes.c_int64 * n)(*[i * cap for i in range(n)])
+        cc = (ctypes.c_int32 * n)(*([cap] * n))
+        counts = (ctypes.c_int32 * n)()
+        p = N.make_params(params)
+        st = self._lib.rd_detect_encoded(self._h, ptr, on_dev, offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         n, ctypes.byref(p), out, oo, cc, counts)
+        N.check(st, "rd_detect_encoded")
+        raw = buf.view(np.uint8)
+        return [_copy_rings(raw, i * cap, counts[i]) for i in range(n)]
+
     def set_tuning(self, stencil_tile: int = 0, vote_lds_kb: int = None, use_graph: bool = True):
         """Launch choices (no result depends on them); vote_lds_kb None keeps the largest."""
         if vote_lds_kb is None:

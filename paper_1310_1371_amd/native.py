@@ -82,6 +82,9 @@ SIGNATURES = {
     "rd_stage_accumulate": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(RdParams), _vp, _vp]),
     "rd_detect_ridges": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(RdParams), _P(RdRing), _i32,
                                         _P(_i32)]),
+    "rd_encode_ridges": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _P(RdParams), _vp, _i64, _P(_i64)]),
+    "rd_detect_encoded": (ctypes.c_int, [_vp, _vp, _i32, _P(_i64), _i32, _P(RdParams), _P(RdRing), _P(_i64),
+                                         _P(_i32), _P(_i32)]),
     "rd_detect_noalloc": (ctypes.c_int, [_P(RdFrame), _P(RdParams), _vp, _vp, _i32, _P(_i32)]),
     "rd_soft_ridges": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp, _vp, _i64, _P(_i64)]),
     "rd_soft_forward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(RdParams), _vp]),
