@@ -99,6 +99,17 @@ int gauss_radius(float sigma) { return static_cast<int>(std::ceil(4.0 * static_c
 
 int vote_tiles(int W, int H) { return ((W + VOTE_TILE - 1) / VOTE_TILE) * ((H + VOTE_TILE - 1) / VOTE_TILE); }
 
+int assign_chunks(rd_ctx* h, int n) {
+    int tot = 0;
+    for (int i = 0; i < n; ++i) {
+        h->h_frames[i].chunk0 = tot;
+        tot += static_cast<int>((static_cast<int64_t>(h->h_frames[i].nbx) * h->h_frames[i].nby + COST_CHUNK - 1) /
+                                COST_CHUNK);
+    }
+    h->n_chunks = tot;
+    return tot;
+}
+
 rd_status check_frame(const rd_ctx* h, const rd_frame* f) {
     if (!f || !f->data) return RD_E_INVALID;
     if (f->dtype != RD_U16 && f->dtype != RD_F32) return RD_E_INVALID;
@@ -145,6 +156,7 @@ rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int var
         bins += static_cast<int64_t>(fd.nbx) * fd.nby;
     }
     if (bins > h->max_bins) return RD_E_TOO_LARGE;
+    assign_chunks(h, n);
     // a call on the same frame buffers (the usual loop) finds its descriptors already there
     if (h->frames_dev_n != n || std::memcmp(h->frames_dev.data(), h->h_frames, n * sizeof(FrameDesc)) != 0) {
         RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, n * sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
@@ -304,7 +316,25 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
         RD_HIP(launch_stencil(stencil_args(h, p, nframes, tt), dtype, rg, h->tune.stencil_tile, false, h->stream));
     }
     RD_TRY(mark(h, 1));
-    RD_HIP(launch_vote(vote_args(h, p, nframes, tv), h->tabs.lds, false, h->cus, h->stream));
+    VoteArgs va = vote_args(h, p, nframes, tv);
+    if (tv <= ORDER_MAX) {
+        // tile costs from sampled votes, then the queue order (costliest tiles first)
+        TileCostArgs ta{};
+        ta.frames = h->d_frames;
+        ta.nframes = nframes;
+        ta.rxy = h->d_rxy;
+        ta.rq = h->d_rq;
+        ta.bin_count = h->d_bin_count;
+        ta.rbase = h->tabs.lbase;
+        ta.rstep = h->tabs.rstep;
+        ta.nlevels = h->tabs.L;
+        ta.total_vtiles = tv;
+        ta.cost = h->d_tcost;
+        ta.order = h->d_torder;
+        RD_HIP(launch_tile_cost(ta, h->n_chunks, h->stream));
+        va.tile_order = h->d_torder;
+    }
+    RD_HIP(launch_vote(va, h->tabs.lds, false, h->cus, h->stream));
     RD_TRY(mark(h, 2));
     RD_HIP(launch_fit(fit_args(h, p, nframes, rings, counts_out), FIT_GRID, h->stream));
     RD_TRY(mark(h, 3));
@@ -331,6 +361,7 @@ rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, in
         k.nchunks = static_cast<int>(h->tabs.chunks.size()) - 1;
         k.blocks = h->cus;
         k.lds = h->tabs.lds;
+        k.bin_chunks = h->n_chunks;
         k.params = p;
         if (!h->gexec[gi] || !(k == h->gkey[gi])) {
             if (h->gexec[gi]) {
@@ -434,6 +465,7 @@ rd_status ridge_setup(rd_ctx* h, const int32_t* xy, const int16_t* q, int64_t n,
     fd.nbx = (W + BIN - 1) / BIN;
     fd.nby = (H + BIN - 1) / BIN;
     h->h_frames[0] = fd;
+    assign_chunks(h, 1);
     RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
     h->frames_dev_n = 0;                          // not a descriptor set setup_frames knows
     return RD_OK;
@@ -614,6 +646,9 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_cbase), h->max_chunks * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_cmeta), (2 * h->max_frames + 4) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_eoff), (h->max_frames + 1) * sizeof(int64_t)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_tcost), ORDER_MAX * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_torder), ORDER_MAX * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMemset(h->d_tcost, 0, ORDER_MAX * sizeof(uint32_t)) == hipSuccess;   // kept zero between launches
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_rings), npk * sizeof(rd_ring), hipHostMallocMapped) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h->h_counts), (h->max_frames + 4) * sizeof(uint32_t),
                              hipHostMallocMapped) == hipSuccess;
@@ -657,6 +692,8 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_cbase);
     (void)hipFree(h->d_cmeta);
     (void)hipFree(h->d_eoff);
+    (void)hipFree(h->d_tcost);
+    (void)hipFree(h->d_torder);
     for (hipEvent_t& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_rings) (void)hipHostFree(h->h_rings);
@@ -932,6 +969,7 @@ rd_status rd_detect_encoded(rd_handle h, const uint8_t* enc, int32_t on_device, 
         px += static_cast<int64_t>(W) * H;
     }
     if (px > h->max_batch_px || bins > h->max_bins) return RD_E_TOO_LARGE;
+    assign_chunks(h, n);
     RD_HIP(hipMemcpyAsync(h->d_frames, h->h_frames, n * sizeof(FrameDesc), hipMemcpyHostToDevice, h->stream));
     h->frames_dev_n = 0;                               // not a descriptor set setup_frames knows
     // the streams on the device: in place, or staged in one copy

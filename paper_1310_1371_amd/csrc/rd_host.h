@@ -57,13 +57,14 @@ inline bool same_params(const rd_params& a, const rd_params& b) {
 // pointers and sizes live in the device-side descriptor table and may change freely.
 struct GraphKey {
     int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, nchunks = 0, blocks = 0;
+    int bin_chunks = 0;
     bool timing = false;   // the graph holds the timing events' record nodes
     size_t lds = 0;
     rd_params params{};
     bool operator==(const GraphKey& o) const {
         return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant && timing == o.timing &&
                total_tiles == o.total_tiles && total_vtiles == o.total_vtiles && nchunks == o.nchunks &&
-               blocks == o.blocks && lds == o.lds && same_params(params, o.params);
+               blocks == o.blocks && lds == o.lds && bin_chunks == o.bin_chunks && same_params(params, o.params);
     }
 };
 
@@ -102,6 +103,11 @@ struct rd_ctx {
     uint32_t* d_cmeta = nullptr;
     int64_t* d_eoff = nullptr;
     int64_t max_chunks = 0;
+    // tile order of the vote kernel (launches of up to ORDER_MAX vote tiles): per-tile cost
+    // estimates (zero between launches) and the order
+    uint32_t* d_tcost = nullptr;
+    uint32_t* d_torder = nullptr;
+    int n_chunks = 0;                   // COST_CHUNK-bin chunks of the current launch's frames
     // pinned host memory; rings and counts are written by the fit kernel through mappings
     rd_ring* h_rings = nullptr;
     rd_ring* dh_rings = nullptr;
@@ -143,6 +149,7 @@ int vote_tiles(int W, int H);
 rd_status check_frame(const rd_ctx* h, const rd_frame* f);
 rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int variant, bool dense, int* total_tiles,
                        int* total_vtiles);
+int assign_chunks(rd_ctx* h, int n);     // chunk0 of h_frames[0 .. n); returns (and keeps) the total
 StencilArgs stencil_args(rd_ctx* h, const rd_params& p, int nframes, int total_tiles);
 rd_status find_ridges(rd_ctx* h, const rd_frame* frame, const rd_params& p);
 rd_status gather_ridges(rd_ctx* h, int32_t* xy, int16_t* q, float* k, int64_t capacity, int64_t* n);

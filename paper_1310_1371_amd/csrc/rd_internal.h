@@ -48,7 +48,7 @@ struct FrameDesc {
     int64_t bin0;        // first ridge bin of this frame
     int32_t nbx, nby;    // bins per row / column
     int32_t peak0;       // first peak slot of this frame
-    int32_t pad;
+    int32_t chunk0;      // first COST_CHUNK-bin chunk of this frame (the tile-cost pass's work units)
 };
 
 constexpr int FRAMES_LDS = 64;   // frame tables up to this size are read into LDS by the kernels
@@ -99,7 +99,30 @@ struct VoteArgs {
     unsigned long long* stats;   // [votes, hotspots, strong] accumulated (may be null)
     uint32_t* acc_dump;          // stage mode (single frame): dense [L][H][W]
     uint64_t* score_dump;
+    const uint32_t* tile_order;  // [total_vtiles] the queue's tiles, estimated costliest first (may be null)
 };
+
+// The tile-cost pass: every (ridge, sign) casts its vote at one level in COST_STEP into a
+// per-tile counter (the tile that holds the vote), an estimate of the tiles' vote work; a
+// second kernel orders the tiles by decreasing cost class.  Launches with more
+// than ORDER_MAX vote tiles are not ordered (with many tiles per workgroup the queue's tail is
+// short anyway).
+constexpr int COST_CHUNK = 8;     // bins per workgroup of the counting kernel
+constexpr int COST_STEP = 8;      // levels per sampled vote
+constexpr int ORDER_MAX = 8192;   // vote tiles of an ordered launch
+struct TileCostArgs {
+    const FrameDesc* frames;
+    int32_t nframes;
+    const uint32_t* rxy;
+    const uint32_t* rq;
+    const uint32_t* bin_count;
+    int32_t rbase, rstep, nlevels;
+    int32_t total_vtiles;        // <= ORDER_MAX
+    uint32_t* cost;              // [ORDER_MAX]: the tiles' counters, zero before the counting kernel and
+                                 // cleared again by the order kernel
+    uint32_t* order;             // [total_vtiles]
+};
+hipError_t launch_tile_cost(const TileCostArgs& a, int total_chunks, hipStream_t s);
 
 struct FitArgs {
     const FrameDesc* frames;

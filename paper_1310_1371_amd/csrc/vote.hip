@@ -160,7 +160,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     for (;;) {
         // tiles are taken from a queue: their cost varies with the number of hotspots
         if (tid == 0) {
-            const int tq = static_cast<int>(atomicAdd(a.tile_counter, 1u));
+            int tq = static_cast<int>(atomicAdd(a.tile_counter, 1u));
+            if (a.tile_order && tq < a.total_vtiles) tq = static_cast<int>(a.tile_order[tq]);   // costliest first
             int fq = 0;                             // last frame whose first vote tile is <= tq
             for (int hi = a.nframes; hi - fq > 1;) {
                 const int mid = (fq + hi) >> 1;
@@ -776,6 +777,105 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     }
 }
 
+// ---- tile order ------------------------------------------------------------------------
+
+constexpr int CNT_ = 256;         // threads of the cost kernel
+constexpr int CWIN = 2048;        // tiles of a workgroup's window (counted in LDS)
+constexpr int ONT = 1024;         // threads of the order kernel
+constexpr int NCLASS = 128;       // cost classes (4 per octave)
+
+// One workgroup per chunk of COST_CHUNK bins; one task per (ridge, sign).  The sampled votes
+// (levels COST_STEP / 2, 3 COST_STEP / 2, ...) land within the last level's radius (plus
+// rounding) of the chunk's strip, so they are counted in LDS over that window of tiles and
+// added to the tiles' counters with one global atomic per (workgroup, tile).
+__global__ __launch_bounds__(CNT_) void k_tile_cost(TileCostArgs a) {
+    __shared__ uint32_t sPre[COST_CHUNK + 1];
+    __shared__ uint32_t sCnt[CWIN];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int cg = static_cast<int>(blockIdx.x);
+    int f = 0;
+    for (int hi = a.nframes; hi - f > 1;) {
+        const int mid = (f + hi) >> 1;
+        if (a.frames[mid].chunk0 <= cg) f = mid; else hi = mid;
+    }
+    const FrameDesc fd = a.frames[f];
+    const int64_t nbins = static_cast<int64_t>(fd.nbx) * fd.nby;
+    const int64_t b0 = static_cast<int64_t>(cg - fd.chunk0) * COST_CHUNK;
+    const int64_t blast = min(b0 + COST_CHUNK, nbins) - 1;
+    if (tid < 64) {                      // ridges per bin of the chunk, as a prefix sum
+        const uint32_t c = (tid < COST_CHUNK && b0 + tid < nbins)
+                               ? min(a.bin_count[fd.bin0 + b0 + tid], static_cast<uint32_t>(BIN_CAP)) : 0u;
+        const uint32_t inc = wave_incl_scan(c, lane);
+        if (tid < COST_CHUNK) sPre[tid + 1] = inc;
+        if (tid == 0) sPre[0] = 0u;
+    }
+    const int T = VOTE_TILE, W = fd.W, H = fd.H;
+    const int tiles_x = (W + T - 1) / T;
+    const int by0 = static_cast<int>(b0 / fd.nbx), by1 = static_cast<int>(blast / fd.nbx);
+    const int bx0 = by0 == by1 ? static_cast<int>(b0 % fd.nbx) : 0;
+    const int bx1 = by0 == by1 ? static_cast<int>(blast % fd.nbx) : fd.nbx - 1;
+    const int reach = a.rbase + a.rstep * (a.nlevels - 1) + 2;
+    const int wx0 = max(0, bx0 * BIN - reach) / T, wx1 = min(W - 1, bx1 * BIN + BIN - 1 + reach) / T;
+    const int wy0 = max(0, by0 * BIN - reach) / T, wy1 = min(H - 1, by1 * BIN + BIN - 1 + reach) / T;
+    const int nwx = wx1 - wx0 + 1;
+    const bool in_lds = nwx * (wy1 - wy0 + 1) <= CWIN;
+    for (int i = tid; i < CWIN; i += CNT_) sCnt[i] = 0u;
+    __syncthreads();
+    const uint32_t total = sPre[COST_CHUNK];
+    for (uint32_t task = tid; task < 2 * total; task += CNT_) {
+        const uint32_t k = task >> 1;
+        const int sg = static_cast<int>(task & 1u);
+        int bi = 0;
+        while (bi + 1 < COST_CHUNK && sPre[bi + 1] <= k) ++bi;
+        const int64_t slot = (fd.bin0 + b0 + bi) * BIN_CAP + (k - sPre[bi]);
+        const uint32_t xy = a.rxy[slot], q = a.rq[slot];
+        const int x = xy & 0xffffu, y = xy >> 16;
+        const int qx = static_cast<int16_t>(q & 0xffffu), qy = static_cast<int16_t>(q >> 16);
+        const int sqx = sg ? -qx : qx, sqy = sg ? -qy : qy, rnd = sg ? 8191 : 8192;
+        for (int l = COST_STEP / 2; l < a.nlevels; l += COST_STEP) {
+            const int r = a.rbase + a.rstep * l;
+            const int vx = x + ((r * sqx + rnd) >> 14), vy = y + ((r * sqy + rnd) >> 14);
+            if (vx < 0 || vx >= W || vy < 0 || vy >= H) continue;
+            const int tx = vx / T, ty = vy / T;
+            if (in_lds && tx >= wx0 && tx <= wx1 && ty >= wy0 && ty <= wy1)
+                atomicAdd(&sCnt[(ty - wy0) * nwx + (tx - wx0)], 1u);
+            else
+                atomicAdd(&a.cost[fd.vtile0 + ty * tiles_x + tx], 1u);
+        }
+    }
+    __syncthreads();
+    if (in_lds)
+        for (int i = tid; i < nwx * (wy1 - wy0 + 1); i += CNT_)
+            if (sCnt[i]) atomicAdd(&a.cost[fd.vtile0 + (wy0 + i / nwx) * tiles_x + wx0 + i % nwx], sCnt[i]);
+}
+
+// One workgroup: each counter read once (and cleared for the next launch), then the order, a
+// counting sort over 4 classes per octave of the cost with the costliest class first (the
+// order within a class is arbitrary: no result depends on the order).
+__global__ __launch_bounds__(ONT) void k_tile_order(TileCostArgs a) {
+    __shared__ uint8_t sCls[ORDER_MAX];
+    __shared__ uint32_t sB[NCLASS];
+    const int tid = threadIdx.x, lane = tid & 63, n = a.total_vtiles;
+    for (int i = tid; i < NCLASS; i += ONT) sB[i] = 0u;
+    __syncthreads();
+    for (int t = tid; t < n; t += ONT) {
+        const uint32_t c = a.cost[t];
+        const int k = c == 0u ? 0 : min(NCLASS - 1, 1 + static_cast<int>(4.0f * __log2f(static_cast<float>(c))));
+        sCls[t] = static_cast<uint8_t>(k);
+        atomicAdd(&sB[k], 1u);
+        a.cost[t] = 0u;
+    }
+    __syncthreads();
+    if (tid < 64) {                                  // class starts, the costliest class first
+        const uint32_t hiC = sB[NCLASS - 1 - 2 * tid], loC = sB[NCLASS - 2 - 2 * tid];
+        const uint32_t inc = wave_incl_scan(hiC + loC, lane);
+        sB[NCLASS - 1 - 2 * tid] = inc - hiC - loC;
+        sB[NCLASS - 2 - 2 * tid] = inc - loC;
+    }
+    __syncthreads();
+    for (int t = tid; t < n; t += ONT) a.order[atomicAdd(&sB[sCls[t]], 1u)] = static_cast<uint32_t>(t);
+}
+
 // Scatter a caller-given ridge list into the per-bin slots, checking what keeps the votes
 // exact: pixels inside the frame, each listed once (one bit per pixel of its bin, taken by an
 // atomic), with a direction code as step 1 makes them.  Any failure sets a flag and the host
@@ -840,6 +940,13 @@ hipError_t launch_gather(const uint32_t* rxy, const uint32_t* rq, const float* r
     const int blocks = static_cast<int>(nbins < 8192 ? nbins : 8192);
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(NT), 0, s, rxy, rq, rk, bin_count, offsets, nbins, xy, q, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_cost(const TileCostArgs& a, int total_chunks, hipStream_t s) {
+    if (a.total_vtiles <= 0 || a.total_vtiles > ORDER_MAX || total_chunks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tile_cost, dim3(total_chunks), dim3(CNT_), 0, s, a);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(ONT), 0, s, a);
     return hipGetLastError();
 }
 
