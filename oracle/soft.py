@@ -307,12 +307,18 @@ LM_DOWN = 1.0 / 3.0
 LM_UP = 4.0
 
 
-def refine(img, theta0, s, iters=20):
-    """(theta, loss) after `iters` Levenberg-Marquardt steps from theta0.  Each step takes
-    the residual e = I - B - A g and its Jacobian J = -A dg/dtheta at the current ring with
-    (A, B) at their optimum there, solves (J^T J + lam diag(J^T J)) d = -J^T e, and keeps
+def refine(img, theta0, s, iters=20, tol=0.0, return_steps=False):
+    """(theta, loss) after at most `iters` Levenberg-Marquardt steps from theta0.  Each step
+    takes the residual e = I - B - A g and its Jacobian J = -A dg/dtheta at the current ring
+    with (A, B) at their optimum there, solves (J^T J + lam diag(J^T J)) d = -J^T e, and keeps
     theta + d only if the loss with (A, B) re-solved is lower; lam is divided by 3 after a
-    kept step and multiplied by 4 otherwise (also when the system is singular)."""
+    kept step and multiplied by 4 otherwise (also when the system is singular).
+
+    READING (convergence, an addition to the fixed step count): the loop ends after a step
+    whose solved update has every component at most `tol` in magnitude, kept or not; a step
+    whose system is singular has no update and does not end it.  tol = 0 stops only on an
+    exactly zero update, after which every further step would repeat it unchanged.  With
+    return_steps the number of steps taken comes third."""
     xs, ys, I_win = _window(img, theta0, s)
 
     def evaluate(th):
@@ -324,7 +330,9 @@ def refine(img, theta0, s, iters=20):
     th = np.array(theta0, dtype=np.float64)
     lam = LM_LAMBDA0
     loss, g, rho, A, e = evaluate(th)
+    steps = 0
     for _ in range(iters):
+        steps += 1
         J = -A * profile_jacobian(xs, ys, th, s, g, rho)
         M = J.T @ J
         try:
@@ -339,7 +347,9 @@ def refine(img, theta0, s, iters=20):
             lam *= LM_DOWN
         else:
             lam *= LM_UP
-    return th, loss
+        if np.max(np.abs(d)) <= tol:
+            break
+    return (th, loss, steps) if return_steps else (th, loss)
 
 
 def render_ring(W, H, theta, s, A, B):

@@ -313,3 +313,48 @@ def test_refine_rejects_a_step_that_raises_the_loss():
     assert np.array_equal(th1, start) and l1 == l0
     th, l20 = S.refine(img, start, 1.5, iters=20)
     assert l20 < l0
+
+
+def test_refine_infinite_tol_takes_exactly_one_step():
+    # every update is within an infinite tolerance, so the first step (kept or not) is the last
+    theta = np.array([40.3, 37.6, 20.45])
+    img = S.render_ring(96, 96, theta, 1.5, 1.0, 0.2)
+    for start in (theta + np.array([0.8, -0.6, 0.7]),                          # first step kept
+                  theta + np.array([0.32201915, -1.17105765, -2.68243943])):   # first step refused
+        th1, l1 = S.refine(img, start, 1.5, iters=1)
+        th, l, n = S.refine(img, start, 1.5, iters=20, tol=np.inf, return_steps=True)
+        assert n == 1 and np.array_equal(th, th1) and l == l1
+
+
+def test_refine_tol_only_truncates_the_steps():
+    # the stopping rule changes nothing but the step count: the same number of fixed steps
+    # gives the same ring and loss, bit for bit; converged rings stop well before 20
+    f = synth.config4(seed=3, n_frames=1, W=256, H=256, n_rings=12)[0]
+    rng = np.random.default_rng(5)
+    counts = []
+    for j in range(len(f.R)):
+        th0 = np.array([f.cx[j], f.cy[j], f.R[j]]) + rng.normal(0, 0.5, 3)
+        th, l, n = S.refine(f.image, th0, 1.5, iters=20, tol=1e-8, return_steps=True)
+        th_fixed, l_fixed = S.refine(f.image, th0, 1.5, iters=n)
+        assert np.array_equal(th, th_fixed) and l == l_fixed
+        th20, _ = S.refine(f.image, th0, 1.5, iters=20)
+        assert np.abs(th - th20).max() <= 1e-7
+        counts.append(n)
+    assert max(counts) < 20 and np.mean(counts) < 10
+
+
+def test_refine_tol_converges_on_noise_free_ring():
+    theta = np.array([40.3, 37.6, 20.45])
+    img = S.render_ring(96, 96, theta, 1.5, 1.0, 0.2)
+    for start in ((0.8, -0.6, 0.7), (-1.0, 0.5, -0.8), (0.3, 0.9, 1.2)):
+        th, loss, n = S.refine(img, theta + np.array(start), 1.5, iters=20, tol=1e-8, return_steps=True)
+        assert n < 10 and np.abs(th - theta).max() <= 1e-6 and loss <= 1e-12
+
+
+def test_refine_singular_steps_do_not_stop():
+    # a zero image: A = 0, so J = 0 and every system is singular; no step has an update,
+    # none ends the loop, the ring stays where it started
+    img = np.zeros((64, 64))
+    start = np.array([30.2, 31.7, 12.4])
+    th, loss, n = S.refine(img, start, 1.5, iters=7, tol=np.inf, return_steps=True)
+    assert n == 7 and np.array_equal(th, start) and loss == 0.0
