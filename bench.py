@@ -48,6 +48,7 @@ sys.path.insert(0, ROOT)
 # its ceiling is the LDS datapath, 256 CUs x 32 banks x 4 bytes per clock at 2.4 GHz (GB/s)
 LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
 POOL_MAX = 16        # worker processes at most (the host share of one GPU)
+LM_TOL = 1e-6       # refinement convergence in the stream leg (pixels)
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "vote_c2_1024_traffic.md")
 
 
@@ -599,7 +600,9 @@ def differentiable(det, args, np, torch, synth):
 def stream(det, args, np, torch, synth):
     """The whole sequence, 32 frames per launch, frames resident in HBM: rendered on the GPU
     (the stream's model, the device's noise) before the timed region.  Each launch: detection,
-    20 LM steps per ring, then the refined rings linked into tracks with depths on the GPU.
+    LM refinement of every ring to convergence (a step whose update is within 1e-6 px in every
+    component is the last; at most 20), then the refined rings linked into tracks with depths
+    on the GPU.
     One untimed warm-up launch on the first 32 frames; then every launch is timed.  Link
     accuracy is scored against the generator's truth afterwards."""
     from paper_1310_1371_amd.tracking import Linker
@@ -619,19 +622,22 @@ def stream(det, args, np, torch, synth):
     frames = store.view(torch.uint16)
     launches = [(k, min(k + 32, n)) for k in range(0, n, 32)]
 
+    steps = []
+
     def run(linker, k0, k1, keep):
         fb = [frames[i] for i in range(k0, k1)]
         res = det.detect_batch(fb, p)
         th0 = torch.from_numpy(np.concatenate([np.stack([r["cx"], r["cy"], r["r"]], 1) for r in res])
                                .astype(np.float64)).cuda()
         fo = torch.cat([torch.full((len(r),), i, dtype=torch.int32, device="cuda") for i, r in enumerate(res)])
-        theta, _ = det.refine(fb, th0, 1.5, iters=20, frame_of=fo)
+        theta, _, nst = det.refine(fb, th0, 1.5, iters=20, frame_of=fo, tol=LM_TOL, return_steps=True)
         offs = np.zeros(len(res) + 1, dtype=np.int32)
         offs[1:] = np.cumsum([len(r) for r in res])
         dets = theta.float().contiguous()
         ids, z = linker.link(dets, offs)
         if keep is not None:
             keep.append((dets, ids, z, offs))
+            steps.append(nst)
         return int(th0.shape[0])
 
     warm = Linker(gate=8.0, memory=2, depth=(8.0, 0.0, 72.0), max_frames=32, stream=det.stream)
@@ -650,6 +656,7 @@ def stream(det, args, np, torch, synth):
     dt = time.perf_counter() - t0
     tracks = linker.info()["tracks"]
     linker.close()
+    st_all = torch.cat(steps).double()
     coded = ridge_streams(det, frames, p, np, torch, args.coded_launches) if args.coded_launches > 0 else None
     del store, frames
     truth = np.stack([xs, ys, st.radius(zs)], 2)
@@ -657,10 +664,13 @@ def stream(det, args, np, torch, synth):
     return {"frames": n, "launches_timed": len(launches), "frames_per_s": n / dt,
             "value": n * st.W * st.H / dt / 1e6, "unit": "Mpixel/s", "ms_per_launch": dt / len(launches) * 1e3,
             "s_total": dt, "rings_detected_and_refined": n_rings, "tracks": tracks, "linking": acc,
+            "lm_steps": {"tol_px": LM_TOL, "max_steps": 20, "mean": float(st_all.mean()),
+                         "max": int(st_all.max()), "at_max": int((st_all >= 20).sum())},
             "s_render_untimed": t_render, "encoded_ridge_streams": coded,
             "workload": f"the whole {n}-frame 2048^2 u16 stream (1000 rings on random walks, radii 8-80), rendered "
                         f"on the GPU and resident in HBM, {len(launches)} launches of up to 32 frames, each: "
-                        "batched detection, 20 LM steps per detection, linking (gate 8 px, memory 2) and depth"}
+                        "batched detection, LM refinement of every detection to convergence (update <= 1e-6 px, "
+                        "at most 20 steps), linking (gate 8 px, memory 2) and depth"}
 
 
 def ridge_streams(det, frames, p, np, torch, launches=4):

@@ -394,14 +394,19 @@ rd_status rd_fit_loss_backward(rd_handle h, const rd_frame* frame, const double*
                                double* grad_theta_dev);
 
 /* Levenberg-Marquardt refinement of m rings over up to 64 device frames (frame_of_dev[j]
- * = frame of ring j, int32; may be NULL when nframes == 1): from theta0_dev, `iters` steps
- * of (J^T J + lam diag J^T J) d = -J^T e on the residuals of L_j with (A, B) re-solved at
- * every point; a step is kept only if it lowers L_j (lam / 3), otherwise lam x 4
- * (lam starts at 1e-3).  Writes theta_dev and, if not NULL, loss_dev (float64).  Rings
- * with a frame index outside [0, nframes) get NaN.  Enqueued. */
+ * = frame of ring j, int32; may be NULL when nframes == 1): from theta0_dev, at most
+ * `iters` steps of (J^T J + lam diag J^T J) d = -J^T e on the residuals of L_j with (A, B)
+ * re-solved at every point; a step is kept only if it lowers L_j (lam / 3), otherwise
+ * lam x 4 (lam starts at 1e-3).  A step whose update d has every component at most tol
+ * (pixels) in magnitude, kept or not, is the ring's last; a singular system gives no update
+ * and does not end the loop; tol = 0 keeps the fixed count (it stops only on d = 0, which
+ * every later step would repeat).  tol must be >= 0 (+inf allowed), else RD_E_INVALID.
+ * Writes theta_dev and, if not NULL, loss_dev (float64) and steps_dev (int32, the steps
+ * taken).  Rings with a frame index outside [0, nframes) get NaN and 0 steps.  Enqueued. */
 rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes,
                     const int32_t* frame_of_dev, const double* theta0_dev, int64_t m, double s,
-                    int32_t iters, double* theta_dev, double* loss_dev);
+                    int32_t iters, double tol, double* theta_dev, double* loss_dev,
+                    int32_t* steps_dev);
 
 /* ---- linking rings into trajectories, depth from radius ------------------------------
  *

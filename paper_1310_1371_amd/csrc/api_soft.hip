@@ -325,9 +325,9 @@ rd_status rd_fit_loss_backward(rd_handle h, const rd_frame* frame, const double*
 }
 
 rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes, const int32_t* frame_of_dev,
-                    const double* theta0_dev, int64_t m, double s, int32_t iters, double* theta_dev,
-                    double* loss_dev) {
-    if (!h || m < 0 || iters < 0 || (m > 0 && (!theta0_dev || !theta_dev))) return RD_E_INVALID;
+                    const double* theta0_dev, int64_t m, double s, int32_t iters, double tol, double* theta_dev,
+                    double* loss_dev, int32_t* steps_dev) {
+    if (!h || m < 0 || iters < 0 || !(tol >= 0.0) || (m > 0 && (!theta0_dev || !theta_dev))) return RD_E_INVALID;
     if (nframes > 1 && m > 0 && !frame_of_dev) return RD_E_INVALID;
     RingArgs a;
     RD_TRY(ring_args(h, frames, nframes, s, &a));
@@ -338,6 +338,8 @@ rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes, const 
     a.theta_out = theta_dev;
     a.loss = loss_dev;
     a.iters = iters;
+    a.tol = tol;
+    a.steps_out = steps_dev;
     a.lam0 = LM_LAMBDA0;
     a.lam_down = LM_DOWN;
     a.lam_up = LM_UP;

@@ -25,7 +25,11 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NW = NT / 64;
-constexpr int WCAP = 6144;   // window members held in LDS (8 bytes each)
+// window members held in LDS (8 bytes each): the loss kernel's list keeps 3 workgroups per CU;
+// the refinement kernel (2 per CU by its registers) lists rings up to r ~ 90 at s = 1.5; above
+// 64 KiB per workgroup the compiler would plan for one workgroup per CU and take more registers
+constexpr int WCAP_LOSS = 6144;
+constexpr int WCAP_REFINE = 7936;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -102,8 +106,11 @@ struct Members {
     bool listed;
 };
 
+// c (optional) receives this thread's part of n, sum I, sum I^2 over the members it lists;
+// when the window does not fit the list, the caller sums them by a walk of the box.
+template <int WCAP>
 __device__ Members build_members(const RingFrame& f, const Window& w, uint32_t* sPos, float* sVal,
-                                 uint32_t* sCnt) {
+                                 uint32_t* sCnt, double* c = nullptr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t nbox = static_cast<int64_t>(w.bw) * w.bh;
     int base = 0;
@@ -130,8 +137,15 @@ __device__ Members build_members(const RingFrame& f, const Window& w, uint32_t* 
         if (mem) {
             const int slot = off + __popcll(ball & ((1ull << lane) - 1ull));
             if (slot < WCAP) {
+                const float v = pixel(f, x, y);
                 sPos[slot] = static_cast<uint32_t>(x - w.x0) | (static_cast<uint32_t>(y - w.y0) << 16);
-                sVal[slot] = pixel(f, x, y);
+                sVal[slot] = v;
+                if (c) {
+                    const double I = static_cast<double>(v);
+                    c[0] += 1.0;
+                    c[1] += I;
+                    c[2] += I * I;
+                }
             }
         }
         base += tot;
@@ -183,8 +197,9 @@ __device__ __forceinline__ Prof profile(const double* th, double inv2s2, double 
 // dg/d(cx, cy, r); at rho = 0 the centre derivatives are taken as 0.
 __device__ __forceinline__ void profile_grad(const Prof& p, const double* th, int x, int y, double d[3]) {
     const double safe = p.rho > 0.0 ? p.rho : 1.0;
-    d[0] = p.dgdrho * (-(x - th[0]) / safe);
-    d[1] = p.dgdrho * (-(y - th[1]) / safe);
+    const double q = p.dgdrho / safe;
+    d[0] = -(x - th[0]) * q;
+    d[1] = -(y - th[1]) * q;
     d[2] = -p.dgdrho;
 }
 
@@ -224,8 +239,8 @@ __device__ void fit_ab(const RingFrame& f, const Window& w, const Members& M, co
 }
 
 __global__ __launch_bounds__(NT) void k_fit_loss(RingArgs a, int backward) {
-    __shared__ uint32_t sPos[WCAP];
-    __shared__ float sVal[WCAP];
+    __shared__ uint32_t sPos[WCAP_LOSS];
+    __shared__ float sVal[WCAP_LOSS];
     __shared__ double sred[NW * 5];
     __shared__ uint32_t sCnt[NW];
     const double inv2s2 = 1.0 / (2.0 * a.s * a.s), invs2 = 1.0 / (a.s * a.s);
@@ -244,7 +259,7 @@ __global__ __launch_bounds__(NT) void k_fit_loss(RingArgs a, int backward) {
         }
         const RingFrame f = a.frames[fi];
         const Window w = make_window(a.theta0 + 3 * j, a.halfwidth, f.W, f.H);
-        const Members M = build_members(f, w, sPos, sVal, sCnt);
+        const Members M = build_members<WCAP_LOSS>(f, w, sPos, sVal, sCnt);
         const double th[3] = {a.theta[3 * j], a.theta[3 * j + 1], a.theta[3 * j + 2]};
         double A, B;
         fit_ab(f, w, M, th, inv2s2, invs2, sred, A, B);
@@ -365,8 +380,8 @@ __device__ LmPoint lm_point(const RingFrame& f, const Window& w, const Members& 
 }
 
 __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
-    __shared__ uint32_t sPos[WCAP];
-    __shared__ float sVal[WCAP];
+    __shared__ uint32_t sPos[WCAP_REFINE];
+    __shared__ float sVal[WCAP_REFINE];
     __shared__ double sred[NW * 18];
     __shared__ uint32_t sCnt[NW];
     const double inv2s2 = 1.0 / (2.0 * a.s * a.s), invs2 = 1.0 / (a.s * a.s);
@@ -376,23 +391,32 @@ __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
             if (threadIdx.x == 0) {
                 for (int c = 0; c < 3; ++c) a.theta_out[3 * j + c] = __builtin_nan("");
                 if (a.loss) a.loss[j] = __builtin_nan("");
+                if (a.steps_out) a.steps_out[j] = 0;
             }
             continue;
         }
         const RingFrame f = a.frames[fi];
         const Window w = make_window(a.theta0 + 3 * j, a.halfwidth, f.W, f.H);
-        const Members M = build_members(f, w, sPos, sVal, sCnt);
         double c[3] = {0, 0, 0};   // n, sum I, sum I^2 over the fixed window
-        for_members(f, w, M, [&](int, int, double I) {
-            c[0] += 1.0;
-            c[1] += I;
-            c[2] += I * I;
-        });
+        const Members M = build_members<WCAP_REFINE>(f, w, sPos, sVal, sCnt, c);
+        if (!M.listed) {
+            c[0] = c[1] = c[2] = 0.0;
+            for_members(f, w, M, [&](int, int, double I) {
+                c[0] += 1.0;
+                c[1] += I;
+                c[2] += I * I;
+            });
+        }
         block_sum<3>(c, sred);
         double th[3] = {a.theta0[3 * j], a.theta0[3 * j + 1], a.theta0[3 * j + 2]};
         double lam = a.lam0;
         LmPoint cur = lm_point(f, w, M, th, c[0], c[1], c[2], inv2s2, invs2, sred);
-        for (int it = 0; it < a.iters; ++it) {
+        int taken = 0;
+        // a converged step lowers the limit to itself; the loop has no early exit, which keeps
+        // the kernel within 256 registers (2 waves per SIMD)
+        int lim = a.iters;
+        for (int it = 0; it < lim; ++it) {
+            ++taken;
             // (J^T J + lam diag(J^T J)) d = -J^T e, solved redundantly by every thread
             const double* J = cur.JtJ;
             double Mx[3][3] = {{J[0] + lam * J[0], J[1], J[2]},
@@ -404,6 +428,10 @@ __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
                 lam *= a.lam_up;
                 continue;
             }
+            // converged: every component of the update within tol (false for a NaN update).
+            // Every thread holds the same sums, so the flag is uniform (read from the first lane)
+            if (__builtin_amdgcn_readfirstlane((fabs(d[0]) <= a.tol && fabs(d[1]) <= a.tol && fabs(d[2]) <= a.tol) ? 1 : 0))
+                lim = it + 1;
             const double cand[3] = {th[0] + d[0], th[1] + d[1], th[2] + d[2]};
             const LmPoint nxt = lm_point(f, w, M, cand, c[0], c[1], c[2], inv2s2, invs2, sred);
             if (nxt.L < cur.L) {
@@ -421,6 +449,7 @@ __global__ __launch_bounds__(NT) void k_refine(RingArgs a) {
             a.theta_out[3 * j + 1] = th[1];
             a.theta_out[3 * j + 2] = th[2];
             if (a.loss) a.loss[j] = cur.L;
+            if (a.steps_out) a.steps_out[j] = taken;
         }
     }
 }

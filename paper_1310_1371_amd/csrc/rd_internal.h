@@ -294,9 +294,11 @@ struct RingArgs {
     const double* grad_loss; // backward: [m] upstream gradient
     float* grad_img;         // backward: [H][W] of frame 0, added into (may be null)
     double* grad_theta;      // backward: [m][3]
-    int32_t iters;           // refinement steps
+    int32_t iters;           // refinement steps, at most
+    double tol;              // a step whose update is within tol in every component is the last
     double lam0, lam_down, lam_up;
     double* theta_out;       // refinement result [m][3]
+    int32_t* steps_out;      // steps taken [m] (may be null)
 };
 
 hipError_t launch_hess_gather(const double* planes, int W, int H, const int32_t* xy, int64_t n, double* hess,

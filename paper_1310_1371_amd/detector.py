@@ -377,9 +377,12 @@ class Detector:
                                                gt.data_ptr()), "rd_fit_loss_backward")
         return grad_img, gt
 
-    def refine(self, frames, theta0, s: float, iters: int = 20, frame_of=None):
-        """Levenberg-Marquardt refinement: (theta float64 [m, 3], loss float64 [m]).  frames is one
-        device frame or a list of up to 64; frame_of gives each ring's frame index."""
+    def refine(self, frames, theta0, s: float, iters: int = 20, frame_of=None, tol: float = 0.0,
+               return_steps: bool = False):
+        """Levenberg-Marquardt refinement: (theta float64 [m, 3], loss float64 [m]), plus the
+        steps taken (int32 [m]) with return_steps.  frames is one device frame or a list of up
+        to 64; frame_of gives each ring's frame index; a step whose update is within tol
+        pixels in every component is a ring's last (tol = 0: `iters` steps)."""
         if not isinstance(frames, (list, tuple)):
             frames = [frames]
         arr = (N.RdFrame * len(frames))(*[_frame_struct(f) for f in frames])
@@ -392,10 +395,12 @@ class Detector:
                 raise ValueError("frame_of must have one entry per ring")
         theta = torch.empty((m, 3), dtype=torch.float64, device=self._dev())
         loss = torch.empty((m,), dtype=torch.float64, device=self._dev())
+        steps = torch.empty((m,), dtype=torch.int32, device=self._dev()) if return_steps else None
         N.check(self._lib.rd_refine(self._h, arr, len(frames), fo.data_ptr() if fo is not None else None,
-                                    theta0.data_ptr(), m, float(s), int(iters), theta.data_ptr(), loss.data_ptr()),
+                                    theta0.data_ptr(), m, float(s), int(iters), float(tol), theta.data_ptr(),
+                                    loss.data_ptr(), steps.data_ptr() if steps is not None else None),
                 "rd_refine")
-        return theta, loss
+        return (theta, loss, steps) if return_steps else (theta, loss)
 
 
 def validate_params(params: dict) -> int:

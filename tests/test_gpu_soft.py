@@ -10,6 +10,7 @@ import torch
 from oracle import ridge_hough as O
 from oracle import soft as S
 from paper_1310_1371_amd import synth
+from paper_1310_1371_amd import native as N
 
 pytestmark = pytest.mark.gpu
 
@@ -208,6 +209,42 @@ def test_refine_matches_oracle(det, c4_frame):
         ref_th, ref_l = S.refine(f.image, th0[j], 1.5, iters=20)
         assert np.abs(th[j] - ref_th).max() <= 1e-6, (j, th[j], ref_th)
         assert abs(loss[j].item() - ref_l) <= 1e-9 * ref_l
+
+
+def test_refine_tol_matches_oracle(det, c4_frame):
+    # the convergence stop: rings, losses and step counts against the oracle's.  The kernel
+    # takes the loss as sum I^2 - A sum I g - B sum I, whose rounding (about 1e-13 here) hides
+    # the loss change of steps below about 2e-8 px, so the tolerance sits well above that
+    f = c4_frame
+    _, th0 = _perturbed(f, 40)
+    th0 = th0 + np.random.default_rng(3).normal(0, 0.5, th0.shape)
+    say(f"[fit] refine {len(th0)} rings, tol 1e-6")
+    th, loss, steps = det.refine(torch.from_numpy(f.image).cuda(), th0, 1.5, iters=20, tol=1e-6, return_steps=True)
+    th, steps = th.cpu().numpy(), steps.cpu().numpy()
+    for j in range(len(th0)):
+        ref_th, ref_l, ref_n = S.refine(f.image, th0[j], 1.5, iters=20, tol=1e-6, return_steps=True)
+        assert steps[j] == ref_n, (j, steps[j], ref_n)
+        assert np.abs(th[j] - ref_th).max() <= 1e-6, (j, th[j], ref_th)
+        assert abs(loss[j].item() - ref_l) <= 1e-9 * ref_l
+    say(f"  steps: mean {steps.mean():.2f}, max {steps.max()}")
+    assert steps.max() < 20
+
+
+def test_refine_tol_limits(det, c4_frame):
+    f = c4_frame
+    img = torch.from_numpy(f.image).cuda()
+    _, th0 = _perturbed(f, 12)
+    th0 = th0 + 0.4
+    # tol = 0 runs every step; an infinite tol stops after the first, equal to iters = 1
+    _, _, n0 = det.refine(img, th0, 1.5, iters=9, tol=0.0, return_steps=True)
+    assert (n0.cpu().numpy() == 9).all()
+    t1, l1 = det.refine(img, th0, 1.5, iters=1)
+    ti, li, ni = det.refine(img, th0, 1.5, iters=20, tol=float("inf"), return_steps=True)
+    assert (ni.cpu().numpy() == 1).all() and torch.equal(t1, ti) and torch.equal(l1, li)
+    for bad in (-1e-9, float("nan")):
+        with pytest.raises(N.RdError) as e:
+            det.refine(img, th0, 1.5, iters=5, tol=bad)
+        assert e.value.status == N.RD_E_INVALID
 
 
 def test_refine_noise_free_ring_converges(det):
