@@ -171,3 +171,77 @@ def test_random_walks_are_recovered():
     ids, tr = _run(frames, gate=12.0, memory=1)
     assert all(i == list(range(len(g))) for i in ids)
     assert len(tr.p) == len(g)
+
+
+# ------------------------------------------------------------------ acceleration model
+
+def _run_model(frames, gate, memory, model):
+    tr = T.Tracker(gate, memory, model=model)
+    return [list(ids) for ids in tr.link([np.array(f, dtype=f32).reshape(-1, 3) for f in frames])], tr
+
+
+def test_constant_acceleration_is_followed_exactly():
+    """x_t = t^2 + t (0, 2, 6, 12, 20): from the third detection on, the quadratic through
+    the last three is exact (weights 1, -3, 3 on integers).  At t = 4 a decoy sits where a
+    constant velocity would put the particle (x_3 + (x_3 - x_2) = 18): the acceleration
+    model takes the true position (cost 0 against 4), the velocity model the decoy."""
+    frames = [[(t * t + t, 40.0, 15.0)] for t in range(4)] + [[(18.0, 40.0, 15.0), (20.0, 40.0, 15.0)]]
+    ids, tr = _run_model(frames, gate=5.0, memory=0, model="acceleration")
+    assert ids == [[0], [0], [0], [0], [1, 0]], ids
+    ids, _ = _run_model(frames, gate=5.0, memory=0, model="velocity")
+    assert ids == [[0], [0], [0], [0], [0, 1]], ids
+    np.testing.assert_array_equal(tr.predict(0, 5), np.array([30, 40, 15], dtype=f32))
+
+
+def test_acceleration_prediction_is_the_polynomial_through_the_history():
+    """Irregular detection times (misses within the memory): the prediction equals the
+    polynomial through the last three detections, and through the only two while the track
+    has two, evaluated by numpy's polynomial fit in float64, to float32 rounding."""
+    rng = np.random.default_rng(7)
+    times = [0, 2, 3, 6, 7, 9]
+    pts = rng.uniform(10, 500, size=(len(times), 3)).astype(f32)
+    frames = [[] for _ in range(max(times) + 1)]
+    for t, p in zip(times, pts):
+        frames[t] = [tuple(p)]
+    tr = T.Tracker(gate=1e6, memory=3, model="acceleration")
+    for t, f in enumerate(frames):
+        if t > 0 and f:
+            hist_t = [tk for tk, _ in tr.hist[0]]
+            hist_q = np.array([q for _, q in tr.hist[0]], dtype=np.float64)
+            for tq in (t, t + 1):
+                want = np.array([np.polyval(np.polyfit(hist_t, hist_q[:, c], len(hist_t) - 1), tq)
+                                 for c in range(3)]) if len(hist_t) > 1 else hist_q[-1]
+                got = tr.predict(0, tq).astype(np.float64)
+                scale = np.abs(hist_q).max() * 24
+                assert np.all(np.abs(got - want) <= 4e-7 * scale), (t, tq, hist_t, got, want)
+        ids = tr.link_frame(np.array(f, dtype=f32).reshape(-1, 3))
+        assert list(ids) == ([0] if f else [])
+    assert [tk for tk, _ in tr.hist[0]] == [6, 7, 9]
+
+
+def test_acceleration_history_starts_with_each_track():
+    """A new track predicts its own position, then the line through two detections (a
+    velocity learnt over a gap of 2 frames): x = 10, then 14 two frames later, then 16 is
+    the line's value one frame on (cost 0, against a decoy at 15, cost 1)."""
+    frames = [[(10.0, 0.0, 9.0)], [], [(14.0, 0.0, 9.0)], [(15.0, 0.0, 9.0), (16.0, 0.0, 9.0)]]
+    ids, tr = _run_model(frames, gate=5.0, memory=1, model="acceleration")
+    assert ids == [[0], [], [0], [1, 0]], ids
+    assert [tk for tk, _ in tr.hist[0]] == [0, 2, 3]
+
+
+def test_models_share_gate_memory_and_matching():
+    """Gate, memory and the greedy tie rules do not depend on the model: a track with one
+    detection predicts its position under both, so these cases give the same ids."""
+    cases = [([[(0, 0, 10), (4, 0, 10)], [(2, 0, 10)]], 3.0, 0),
+             ([[(0, 0, 10)], [(0, 2, 10), (0, -2, 10)]], 3.0, 0),
+             ([[(5, 5, 9)], [], [], [(5, 5, 9)]], 1.0, 2),
+             ([[(5, 5, 9)], [], [], [(5, 5, 9)]], 1.0, 1)]
+    for frames, gate, mem in cases:
+        a, _ = _run_model(frames, gate, mem, "velocity")
+        b, _ = _run_model(frames, gate, mem, "acceleration")
+        assert a == b, (frames, a, b)
+
+
+def test_unknown_model_is_refused():
+    with pytest.raises(ValueError):
+        T.Tracker(1.0, 0, model="jerk")
