@@ -426,8 +426,18 @@ rd_status rd_refine(rd_handle h, const rd_frame* frames, int32_t nframes,
  *   - a matched track gets v = (d - p) / g, p = d, t_l = t; each unmatched detection opens a
  *     track (v = 0), ids in increasing detection order;
  *   - depth z(r) = larger root of c2 z^2 + c1 z + c0 - r = 0 for c2 > 0, the discriminant
- *     clamped at 0. */
+ *     clamped at 0.
+ * The paper's linker also accounts for accelerations in its kinematic model (Methods,
+ * "Precision assessment").  With model = RD_LINK_ACCELERATION a track keeps its last three
+ * detections (t_k, q_k), t_0 < t_1 < t_2 = t_l (fewer while it is young), and predicts with
+ * the polynomial through them at frame t in Lagrange form: p^ = q_2 with one detection,
+ * w_2 q_2 + w_1 q_1 with two, (w_2 q_2 + w_1 q_1) + w_0 q_0 with three, where
+ * w_k = prod_{m != k} (t - t_m) / prod_{m != k} (t_k - t_m), numerator and denominator exact
+ * integers converted to float32 and divided in float32; a match appends (t, d) and drops
+ * the oldest detection beyond three.  Gate, memory, matching and ids are as above. */
 
+#define RD_LINK_VELOCITY 0             /* prediction p + v g                         */
+#define RD_LINK_ACCELERATION 1         /* polynomial through the last three detections */
 #define RD_LINK_MAX_DETECTIONS 4096   /* detections in one frame                    */
 #define RD_LINK_MAX_ACTIVE 6144       /* tracks taking part in one frame            */
 
@@ -438,6 +448,7 @@ typedef struct {
                           c2 > 0, else rd_linker_create returns RD_E_INVALID              */
     double depth_c1;
     double depth_c2;
+    int32_t model;     /* RD_LINK_VELOCITY or RD_LINK_ACCELERATION                      */
 } rd_link_params;
 
 typedef struct rd_linker_s* rd_linker;

@@ -4,9 +4,11 @@
 // has a memory for missed frames (Methods, "Experimental details"), and converts a ring's
 // radius into depth through the larger root of a quadratic calibration (SI, calibration
 // curve figure).  The tracker itself is not printed; the one here:
-//   prediction p^ = p + v g (g = frames since the track was last seen), cost
-//   c = |p^ - d|^2 over (x, y, r), candidates c <= gate^2, and the greedy matching that takes
-//   candidates in increasing (c, track id, detection index) order.
+//   prediction p^ = p + v g (g = frames since the track was last seen), or, in the
+//   acceleration model (the paper's linker accounts for accelerations: Methods, "Precision
+//   assessment"), the Lagrange polynomial through the track's last three detections at
+//   their frames; cost c = |p^ - d|^2 over (x, y, r), candidates c <= gate^2, and the greedy
+//   matching that takes candidates in increasing (c, track id, detection index) order.
 //
 // The greedy matching is found without sorting: with a strict total order on the candidate
 // pairs, the greedy result is the union of rounds of "locally dominant" pairs, each pair the
@@ -51,9 +53,12 @@ struct Args {
     double c0, c1, c2;
     float gate;
     int32_t memory;
+    int32_t model;             // RD_LINK_VELOCITY or RD_LINK_ACCELERATION
     float* pos;                // 3 floats per track: last (x, y, r)
-    float* vel;                // 3 floats per track
+    float* vel;                // 3 floats per track (velocity model)
     int32_t* t_last;           // per track
+    float* hist;               // acceleration model: 6 floats per track, q_0 then q_1
+    int32_t* hist_t;           // acceleration model: 2 ints per track, t_0 then t_1 (-1: none)
     int32_t* act0;             // active lists, double-buffered across frames
     int32_t* act1;
     int32_t* state;            // S_COUNT words
@@ -167,10 +172,34 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
             const int slot = atomicAdd(&s_keep, 1);
             if (slot >= MAX_ACTIVE) { atomicOr(&s_err, ERR_ACTIVE); continue; }
             act_out[slot] = i;
-            const float g = (float)gap;
-            const float px = A.pos[3 * i] + A.vel[3 * i] * g;
-            const float py = A.pos[3 * i + 1] + A.vel[3 * i + 1] * g;
-            const float pr = A.pos[3 * i + 2] + A.vel[3 * i + 2] * g;
+            float px, py, pr;
+            if (A.model == RD_LINK_VELOCITY) {
+                const float g = (float)gap;
+                px = A.pos[3 * i] + A.vel[3 * i] * g;
+                py = A.pos[3 * i + 1] + A.vel[3 * i + 1] * g;
+                pr = A.pos[3 * i + 2] + A.vel[3 * i + 2] * g;
+            } else {
+                const int64_t t2 = A.t_last[i], t1 = A.hist_t[2 * i + 1], t0 = A.hist_t[2 * i];
+                const float* q1 = A.hist + 6 * (int64_t)i + 3;
+                const float* q0 = A.hist + 6 * (int64_t)i;
+                px = A.pos[3 * i];
+                py = A.pos[3 * i + 1];
+                pr = A.pos[3 * i + 2];
+                if (t1 >= 0 && t0 < 0) {                      // the line through two
+                    const float w2 = (float)(t - t1) / (float)(t2 - t1);
+                    const float w1 = (float)(t - t2) / (float)(t1 - t2);
+                    px = w2 * px + w1 * q1[0];
+                    py = w2 * py + w1 * q1[1];
+                    pr = w2 * pr + w1 * q1[2];
+                } else if (t1 >= 0) {                         // the parabola through three
+                    const float w2 = (float)((t - t1) * (t - t0)) / (float)((t2 - t1) * (t2 - t0));
+                    const float w1 = (float)((t - t2) * (t - t0)) / (float)((t1 - t2) * (t1 - t0));
+                    const float w0 = (float)((t - t2) * (t - t1)) / (float)((t0 - t2) * (t0 - t1));
+                    px = (w2 * px + w1 * q1[0]) + w0 * q0[0];
+                    py = (w2 * py + w1 * q1[1]) + w0 * q0[1];
+                    pr = (w2 * pr + w1 * q1[2]) + w0 * q0[2];
+                }
+            }
             auto test = [&](int j) {
                 const float dx = px - sx[j], dy = py - sy[j], dr = pr - sr[j];
                 const float c = dx * dx + dy * dy + dr * dr;
@@ -252,10 +281,20 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
                 int id;
                 if (!fresh) {
                     id = act_out[(int)md[j] - 1];
-                    const float g = (float)(t - A.t_last[id]);
-                    A.vel[3 * id] = (d.x - A.pos[3 * id]) / g;
-                    A.vel[3 * id + 1] = (d.y - A.pos[3 * id + 1]) / g;
-                    A.vel[3 * id + 2] = (d.z - A.pos[3 * id + 2]) / g;
+                    if (A.model == RD_LINK_VELOCITY) {
+                        const float g = (float)(t - A.t_last[id]);
+                        A.vel[3 * id] = (d.x - A.pos[3 * id]) / g;
+                        A.vel[3 * id + 1] = (d.y - A.pos[3 * id + 1]) / g;
+                        A.vel[3 * id + 2] = (d.z - A.pos[3 * id + 2]) / g;
+                    } else {                                  // the history moves down one
+                        float* h = A.hist + 6 * (int64_t)id;
+                        for (int c = 0; c < 3; ++c) {
+                            h[c] = h[3 + c];
+                            h[3 + c] = A.pos[3 * id + c];
+                        }
+                        A.hist_t[2 * id] = A.hist_t[2 * id + 1];
+                        A.hist_t[2 * id + 1] = A.t_last[id];
+                    }
                 } else {
                     id = ntracks + before;
                     const int slot = keep + before;
@@ -263,9 +302,14 @@ __global__ __launch_bounds__(THREADS) void k_link(Args A) {
                     else if (slot >= MAX_ACTIVE) { atomicOr(&s_err, ERR_ACTIVE); id = -1; }
                     else {
                         act_out[slot] = id;
-                        A.vel[3 * id] = 0.f;
-                        A.vel[3 * id + 1] = 0.f;
-                        A.vel[3 * id + 2] = 0.f;
+                        if (A.model == RD_LINK_VELOCITY) {
+                            A.vel[3 * id] = 0.f;
+                            A.vel[3 * id + 1] = 0.f;
+                            A.vel[3 * id + 2] = 0.f;
+                        } else {
+                            A.hist_t[2 * id] = -1;
+                            A.hist_t[2 * id + 1] = -1;
+                        }
                     }
                 }
                 if (id >= 0) {
@@ -309,8 +353,8 @@ struct rd_linker_s {
     rd_link_params p{};
     int32_t max_tracks = 0, max_edges = 0;
     hipStream_t stream = nullptr;
-    float *pos = nullptr, *vel = nullptr;
-    int32_t *t_last = nullptr, *act0 = nullptr, *act1 = nullptr, *state = nullptr, *offsets = nullptr;
+    float *pos = nullptr, *vel = nullptr, *hist = nullptr;
+    int32_t *t_last = nullptr, *hist_t = nullptr, *act0 = nullptr, *act1 = nullptr, *state = nullptr, *offsets = nullptr;
     uint4* edges = nullptr;
     int32_t max_frames = 0;
     int32_t* h_state = nullptr;   // pinned
@@ -318,6 +362,7 @@ struct rd_linker_s {
 
 static void linker_free(rd_linker_s* L) {
     (void)hipFree(L->pos); (void)hipFree(L->vel); (void)hipFree(L->t_last); (void)hipFree(L->act0); (void)hipFree(L->act1);
+    (void)hipFree(L->hist); (void)hipFree(L->hist_t);
     (void)hipFree(L->state); (void)hipFree(L->offsets); (void)hipFree(L->edges);
     if (L->h_state) (void)hipHostFree(L->h_state);
     delete L;
@@ -326,7 +371,7 @@ static void linker_free(rd_linker_s* L) {
 static bool link_params_ok(const rd_link_params* p) {
     return p && p->gate > 0.f && p->gate < 1e18f && p->memory >= 0 && p->memory < (1 << 20) &&
            std::isfinite(p->depth_c0) && std::isfinite(p->depth_c1) && std::isfinite(p->depth_c2) &&
-           p->depth_c2 > 0.0;
+           p->depth_c2 > 0.0 && (p->model == RD_LINK_VELOCITY || p->model == RD_LINK_ACCELERATION);
 }
 
 extern "C" rd_status rd_linker_create(const rd_link_params* params, int32_t max_tracks,
@@ -353,7 +398,10 @@ extern "C" rd_status rd_linker_create(const rd_link_params* params, int32_t max_
         hipMalloc(&L->state, S_COUNT * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&L->offsets, ((size_t)max_frames + 1) * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&L->edges, (size_t)L->max_edges * sizeof(uint4)) != hipSuccess ||
-        hipHostMalloc(&L->h_state, S_COUNT * sizeof(int32_t)) != hipSuccess) {
+        hipHostMalloc(&L->h_state, S_COUNT * sizeof(int32_t)) != hipSuccess ||
+        (params->model == RD_LINK_ACCELERATION &&
+         (hipMalloc(&L->hist, nt * 6 * sizeof(float)) != hipSuccess ||
+          hipMalloc(&L->hist_t, nt * 2 * sizeof(int32_t)) != hipSuccess))) {
         linker_free(L);
         return RD_E_NOMEM;
     }
@@ -412,9 +460,12 @@ extern "C" rd_status rd_link(rd_linker L, const float* det_dev, const int32_t* f
     a.c2 = L->p.depth_c2;
     a.gate = L->p.gate;
     a.memory = L->p.memory;
+    a.model = L->p.model;
     a.pos = L->pos;
     a.vel = L->vel;
     a.t_last = L->t_last;
+    a.hist = L->hist;
+    a.hist_t = L->hist_t;
     a.act0 = L->act0;
     a.act1 = L->act1;
     a.state = L->state;

@@ -45,7 +45,7 @@ class RdTuning(ctypes.Structure):
 
 class RdLinkParams(ctypes.Structure):
     _fields_ = [("gate", ctypes.c_float), ("memory", ctypes.c_int32), ("depth_c0", ctypes.c_double),
-                ("depth_c1", ctypes.c_double), ("depth_c2", ctypes.c_double)]
+                ("depth_c1", ctypes.c_double), ("depth_c2", ctypes.c_double), ("model", ctypes.c_int32)]
 
 
 class RdError(RuntimeError):

@@ -1,8 +1,9 @@
 """Linking detected rings into trajectories on the GPU, and depth from radius: a thin
 binding of the rd_link* entry points (argument marshalling only; every step runs in the
-HIP kernel).  The tracker (prediction from the last velocity, gate, greedy matching in
-(cost, track id, detection index) order, memory for missed frames) is defined where the
-entry points are declared, in ridge_detect.h."""
+HIP kernel).  The tracker (prediction from the last velocity, or from the polynomial through
+the last three detections, gate, greedy matching in (cost, track id, detection index) order,
+memory for missed frames) is defined where the entry points are declared, in
+ridge_detect.h."""
 from __future__ import annotations
 
 import ctypes
@@ -14,6 +15,7 @@ from . import native as N
 
 MAX_DETECTIONS = 4096
 MAX_ACTIVE = 6144
+MODELS = {"velocity": 0, "acceleration": 1}
 
 
 class Linker:
@@ -22,11 +24,14 @@ class Linker:
     rings."""
 
     def __init__(self, gate: float, memory: int, depth=(8.0, 0.0, 72.0), max_tracks: int = 1 << 20,
-                 max_frames: int = 256, stream: torch.cuda.Stream | None = None):
+                 max_frames: int = 256, stream: torch.cuda.Stream | None = None, model: str = "velocity"):
         if not torch.cuda.is_available():
             raise RuntimeError("the linker needs a HIP device")
+        if model not in MODELS:
+            raise ValueError(f"model must be one of {list(MODELS)}")
         self._lib = N.lib()
-        self.params = N.RdLinkParams(float(gate), int(memory), float(depth[0]), float(depth[1]), float(depth[2]))
+        self.params = N.RdLinkParams(float(gate), int(memory), float(depth[0]), float(depth[1]), float(depth[2]),
+                                     MODELS[model])
         self.stream = stream or torch.cuda.current_stream()
         self.max_frames = int(max_frames)
         h = ctypes.c_void_p()

@@ -217,3 +217,99 @@ def test_active_overflow_leaves_no_stale_slot(linker_cls):
     nt, na, frame = lk._info_raw()
     assert nt == 6144 and na == 6144 and frame == 3
     lk.close()
+
+
+# ------------------------------------------------------------------ acceleration model
+
+def _curved_frames(seed, n, n_frames, box=300.0, speed=2.0, R=3.0, noise=0.02):
+    """Crowded particles on tight circles (R px, speed px per frame, either sense), seen
+    with small noise, shuffled; returns the frames and each detection's particle."""
+    rng = np.random.default_rng(seed)
+    cx, cy = rng.uniform(0, box, n), rng.uniform(0, box, n)
+    om = speed / R * rng.choice([-1, 1], n)
+    ph, r = rng.uniform(0, 2 * np.pi, n), rng.uniform(10, 60, n)
+    frames, truth = [], []
+    for t in range(n_frames):
+        a = ph + om * t
+        d = np.stack([cx + R * np.cos(a), cy + R * np.sin(a), r], 1) + rng.normal(0, noise, (n, 3))
+        perm = rng.permutation(n)
+        frames.append(d[perm].astype(f32))
+        truth.append(perm)
+    return frames, truth
+
+
+def _wrong_links(ids, offs, truth):
+    last, wrong = {}, 0
+    for f, tt in enumerate(truth):
+        for i, p in zip(ids[offs[f]:offs[f + 1]], tt):
+            wrong += p in last and last[p] != i
+            last[p] = i
+    return wrong
+
+
+@pytest.mark.parametrize("gate,memory", [(8.0, 2), (4.0, 0)])
+def test_acceleration_random_walks_over_two_calls(linker_cls, gate, memory):
+    say(f"[track] acceleration model: 1200 walking particles, calls of 25 + 15, gate {gate}, memory {memory}")
+    frames = _walk_frames(12, 1200, 40)
+    lk = linker_cls(gate, memory, model="acceleration")
+    tr = T.Tracker(gate, memory, model="acceleration")
+    _check(lk, tr, frames[:25])
+    _check(lk, tr, frames[25:])
+    assert lk.info()["tracks"] == len(tr.p)
+    lk.close()
+
+
+def test_acceleration_on_curved_paths(linker_cls):
+    """Turning particles in a crowd (800 on circles of 3 px at 2 px per frame, gate 3,
+    memory 2): ids bit-exact against the oracle for both models, and the acceleration model,
+    whose prediction follows the turn, makes fewer wrong links than the constant velocity."""
+    say("[track] curved paths in a crowd, both models")
+    frames, truth = _curved_frames(1, 800, 30)
+    wrong = {}
+    for model in ("velocity", "acceleration"):
+        lk = linker_cls(3.0, 2, model=model)
+        tr = T.Tracker(3.0, 2, model=model)
+        _check(lk, tr, frames[:17])
+        _check(lk, tr, frames[17:])
+        lk.close()
+        ref = T.Tracker(3.0, 2, model=model)
+        ids = np.concatenate([ref.link_frame(f) for f in frames])
+        offs = np.concatenate([[0], np.cumsum([len(f) for f in frames])])
+        wrong[model] = _wrong_links(ids, offs, truth)
+    say(f"  wrong links over {sum(len(f) for f in frames[1:])}: {wrong}")
+    assert wrong["acceleration"] < 0.6 * wrong["velocity"]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_acceleration_lattice_ties_and_gaps(linker_cls, seed):
+    say(f"[track] acceleration model, crowded lattice, seed {seed}")
+    frames = _lattice_frames(seed + 10, 300, 30)
+    frames[7] = frames[7][:0]
+    lk = linker_cls(3.0, 2, model="acceleration")
+    _check(lk, T.Tracker(3.0, 2, model="acceleration"), frames)
+    lk.close()
+
+
+def test_acceleration_far_and_non_finite(linker_cls):
+    say("[track] acceleration model, far and non-finite coordinates")
+    frames = _walk_frames(22, 300, 10)
+    rng = np.random.default_rng(5)
+    far = np.stack([131000.0 + 40.0 * np.arange(20), np.full(20, -5.0), np.full(20, 30.0)], 1)
+    out = []
+    for t, f in enumerate(frames):
+        extra = far + np.array([4.0 * t + 0.5 * t * t, 1.0 * t, 0.0])
+        bad = np.array([[np.nan, 10.0, 10.0], [10.0, np.inf, 10.0], [5.0, 5.0, np.nan]])
+        d = np.concatenate([f, extra, bad]).astype(f32)
+        out.append(d[rng.permutation(len(d))])
+    lk = linker_cls(6.0, 1, model="acceleration")
+    with np.errstate(invalid="ignore"):
+        _check(lk, T.Tracker(6.0, 1, model="acceleration"), out)
+    lk.close()
+
+
+def test_linker_rejects_unknown_model():
+    import ctypes
+    from paper_1310_1371_amd import native as N
+    p = N.RdLinkParams(5.0, 1, 8.0, 0.0, 72.0, 2)
+    h = ctypes.c_void_p()
+    assert N.lib().rd_linker_create(ctypes.byref(p), 100, 4, None, ctypes.byref(h)) == N.RD_E_INVALID
