@@ -394,6 +394,24 @@ def main():
                                            "hbm_GBs": (2.0 * args.batch * px + 12.0 * nr_b) / st_s / 1e9,
                                            "hbm_frac": (2.0 * args.batch * px + 12.0 * nr_b) / st_s / 8e12},
                           "workload": f"{args.batch} frames of 1024x1024 u16, 200 rings each (seeds 1000..)"}
+        # the same batch with steps 1-2 in float32 (rd_params.curvature_fp32)
+        p32 = dict(p, curvature_fp32=1)
+        for _ in range(2):
+            det.detect_batch(frames, p32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            det.detect_batch(frames, p32)
+        torch.cuda.synchronize()
+        dt32 = (time.perf_counter() - t0) / args.batch_steps
+        det.enable_timing(True)
+        det.read_timing(reset=True)
+        det.detect_batch(frames, p32)
+        ms32 = det.read_timing(reset=True)["ridge"]
+        det.enable_timing(False)
+        out["batched"]["curvature_fp32"] = {"value": args.batch * px / dt32 / 1e6, "unit": "Mpixel/s",
+                                            "ms_per_batch": dt32 * 1e3, "ridge_kernel_ms": ms32[0] / max(ms32[1], 1),
+                                            "vs_plain": (args.batch * px / dt32 / 1e6) / value}
         del frames
 
     # ---- uneven batch, with the launch shapes the autotuner picks for it

@@ -98,6 +98,13 @@ typedef struct {
                                  top level's radius <= 127.  s = 1 is the plain method.  The annulus half-width
                                  should cover half a step (w >= s / 2 + 1).  rd_soft_forward and
                                  rd_soft_backward take s = 1 only. */
+    int32_t curvature_fp32;   /* 0: steps 1-2 filter in float64 (the default); 1: in float32,
+                                 after the mean of each tile's input (with its halo) is taken
+                                 out of its pixels, which the second derivatives cancel.  k_-
+                                 then agrees with the float64 path to about 1e-6 of max|k_-|;
+                                 ridge decisions within that of the threshold or of a
+                                 neighbour can differ.  The differentiable entry points take
+                                 0 only. */
 } rd_params;
 
 /* One detected ring.  (a, b, r_bin) is the Hough peak voxel; (cx, cy, r) the circle fit

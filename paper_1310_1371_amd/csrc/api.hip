@@ -92,6 +92,7 @@ StencilArgs stencil_args_for(const rd_params& p, const FrameDesc* frames, int nf
     for (int i = 0; i <= RG_MAX; ++i) a.g[i] = i <= R ? g[i] / sum : 0.0;
     a.k_threshold = p.k_threshold;
     a.edge = p.measure == RD_MEASURE_EDGE ? 1 : 0;
+    a.fp32 = p.curvature_fp32 ? 1 : 0;
     return a;
 }
 
@@ -559,6 +560,7 @@ rd_status rd_validate_params(const rd_params* p) {
     if (p->annulus_halfwidth < 0 || p->annulus_halfwidth > 64) return RD_E_INVALID;
     if (p->min_fit_points < 3) return RD_E_INVALID;
     if (p->measure != RD_MEASURE_RIDGE && p->measure != RD_MEASURE_EDGE) return RD_E_INVALID;
+    if (p->curvature_fp32 != 0 && p->curvature_fp32 != 1) return RD_E_INVALID;
     return RD_OK;
 }
 

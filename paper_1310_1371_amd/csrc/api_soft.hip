@@ -118,6 +118,7 @@ rd_status rd_soft_ridges(rd_handle h, const rd_frame* frame, const rd_params* pa
     *n_ridges = 0;
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
+    if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
     RD_TRY(check_frame(h, frame));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;
@@ -145,6 +146,7 @@ rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess
     if (!h || !params || !acc_dev || n < 0 || (n > 0 && (!xy_dev || !hess_dev))) return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
+    if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
     if (param_rstep(*params) != 1) return RD_E_INVALID;             // levels in steps of one pixel
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
@@ -194,6 +196,7 @@ rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hes
         return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
+    if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
     if (param_rstep(*params) != 1) return RD_E_INVALID;             // levels in steps of one pixel
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
@@ -224,6 +227,7 @@ rd_status rd_hessian_backward(rd_handle h, const int32_t* xy_dev, const double* 
     if (!h || !params || !grad_img_dev || n < 0 || (n > 0 && (!xy_dev || !grad_hess_dev))) return RD_E_INVALID;
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
+    if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;

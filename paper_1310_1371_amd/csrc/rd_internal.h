@@ -65,6 +65,7 @@ struct StencilArgs {
     double g[RG_MAX + 1];    // g[0] centre tap, g[i] = g[-i]; zero beyond the radius
     double k_threshold;
     int32_t edge;            // 1: directed edges (m = -|grad I|, unit-gradient codes); 0: ridges
+    int32_t fp32;            // 1: float32 filters on the tile-mean-offset image; 0: float64
     uint32_t* rxy;           // ridge (x | y << 16) per slot
     uint32_t* rq;            // ridge (qx & 0xffff | qy << 16) per slot
     float* rk;               // ridge k_- per slot

@@ -12,10 +12,14 @@
 // smoothed image, the Hessian or k_- ever goes to memory (except in the dense stage mode,
 // which writes k_- and q, and optionally the Hessian planes, of a single frame).
 //
-// The filters run in fp64: the Hessian is a small difference of large smoothed values
-// (e.g. a 12-bit frame with a 600-count background and curvatures of order 1 count/px^2),
-// so fp32 would lose about 1e-4 absolute, far above the 1e-5 relative agreement the
-// results are held to.  CDNA fp64 FMA issues at the fp32 (non-packed) rate.
+// The filters run in fp64 by default: the Hessian is a small difference of large smoothed
+// values (e.g. a 12-bit frame with a 600-count background and curvatures of order 1
+// count/px^2).  CDNA fp64 FMA issues at the fp32 (non-packed) rate, so fp64 costs no issue
+// slots, only registers and LDS.  The fp32 variant (rd_params.curvature_fp32) first takes the
+// mean of the loaded tile out of every input pixel: second derivatives are blind to a
+// constant, so this changes only the magnitude the filters carry, and with it the rounding.
+// It halves the LDS planes and the registers of the filter windows, which lets three
+// workgroups share a CU where the fp64 kernel fits two.
 //
 // Single reflect-101 extension of the raw image is enough for the two-step definition
 // (blur with mirrored borders, then Sobel with mirrored borders): with a symmetric
@@ -81,8 +85,9 @@ __device__ __forceinline__ void nms_offset(uint32_t q, int& nx, int& ny) {
     }
 }
 
-template <int TW_, int TH_, int RG_>
+template <int TW_, int TH_, int RG_, typename TC_>
 struct StencilShape {
+    using TC = TC_;                                // filter arithmetic: double or float
     static constexpr int TW = TW_, TH = TH_, RG = RG_;
     static constexpr int HALO = RG + 3;            // Gaussian + Sobel + NMS neighbour
     static constexpr int IW = TW + 2 * HALO;       // input tile
@@ -96,21 +101,26 @@ struct StencilShape {
     static constexpr int MS = 6;                   // Sobel/eigen pass
     static constexpr int NBX = TW / BIN, NBY = TH / BIN;
     static constexpr int SZ_I = IH * IWP * 4;
-    static constexpr int SZ_G = GH * HC * 8;
-    static constexpr int SZ_H = IH * HC * 8;
-    static constexpr int SZ_K = KH * KW * 8;
+    static constexpr int SZ_G = GH * HC * (int)sizeof(TC);
+    static constexpr int SZ_H = IH * HC * (int)sizeof(TC);
+    static constexpr int SZ_K = KH * KW * (int)sizeof(TC);
     static constexpr int SZ_Q = KH * KW * 4;
     static constexpr int SZ_A = SZ_I > SZ_G ? SZ_I : SZ_G;
     static constexpr int SZ_B = SZ_H > (SZ_K + SZ_Q) ? SZ_H : (SZ_K + SZ_Q);
     static constexpr int LDS = SZ_A + SZ_B;
     static_assert(TW % BIN == 0 && TH % BIN == 0, "tiles hold whole bins");
     static_assert(LDS <= 65536, "static LDS limit");
+    // workgroups per CU the register allocation plans for: three for the fp32 kernel up to
+    // RG = 8 (168 registers, a few spilled; its LDS allows it), else what the registers give
+    static constexpr int MINB = (sizeof(TC) == 4 && RG <= 8 && 3 * LDS <= 160 * 1024) ? 3 : 1;
 };
 
 constexpr int NT = 256;
 
 template <typename TIN, typename SH, bool DENSE>
-__global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
+__global__ __launch_bounds__(NT, SH::MINB) void k_stencil(StencilArgs a) {
+    using TC = typename SH::TC;
+    constexpr bool F32 = sizeof(TC) == 4;
     constexpr int TW = SH::TW, TH = SH::TH, RG = SH::RG, HALO = SH::HALO;
     constexpr int IW = SH::IW, IH = SH::IH, IWP = SH::IWP, HC = SH::HC, GH = SH::GH;
     constexpr int KW = SH::KW, KH = SH::KH, MH = SH::MH, MV = SH::MV, MS = SH::MS;
@@ -120,16 +130,20 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
     __shared__ uint32_t wcount[NB][NT / 64];
     // the frame table of a launch of up to FRAMES_LDS frames, read once per workgroup
     __shared__ FrameDesc sFr[FRAMES_LDS];
+    __shared__ float sRed[NT / 64];                             // fp32: the tile mean
     float* sI = reinterpret_cast<float*>(smem);                 // region A
-    double* sG = reinterpret_cast<double*>(smem);               // region A (after sI dies)
-    double* sH = reinterpret_cast<double*>(smem + SH::SZ_A);    // region B
-    double* sK = reinterpret_cast<double*>(smem + SH::SZ_A);    // region B (after sH dies)
+    TC* sG = reinterpret_cast<TC*>(smem);                       // region A (after sI dies)
+    TC* sH = reinterpret_cast<TC*>(smem + SH::SZ_A);            // region B
+    TC* sK = reinterpret_cast<TC*>(smem + SH::SZ_A);            // region B (after sH dies)
     uint32_t* sQ = reinterpret_cast<uint32_t*>(smem + SH::SZ_A + SH::SZ_K);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const double kthr = a.k_threshold;
+    const TC kthr = static_cast<TC>(a.k_threshold);
+    TC gw[RG + 1];                                              // Gaussian taps
+#pragma unroll
+    for (int i = 0; i <= RG; ++i) gw[i] = static_cast<TC>(a.g[i]);
 
     const bool fr_lds = a.nframes <= FRAMES_LDS;
     if (fr_lds) {
@@ -153,6 +167,7 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
 
         // ---- load the input tile with mirrored borders: a thread's loads (up to twenty at a
         // time) are all issued before any of them is stored, so their latencies overlap
+        float part = 0.0f;                          // fp32: this thread's share of the tile sum
         {
             constexpr int NLD = (IH * IW + NT - 1) / NT, G = NLD < 20 ? NLD : 20;
 #pragma unroll
@@ -175,8 +190,22 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
                     if (k0 + k < NLD && i < IH * IW) {
                         const int r = i / IW, c = i - r * IW;
                         sI[r * IWP + c] = v[k];
+                        if (F32) part += v[k];
                     }
                 }
+            }
+        }
+        if (F32) {
+            // the tile mean out of every pixel (any constant would do: it cancels in the
+            // second derivatives, up to rounding)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+            if (lane == 0) sRed[wave] = part;
+            __syncthreads();
+            const float mean = ((sRed[0] + sRed[1]) + (sRed[2] + sRed[3])) * (1.0f / (IH * IW));
+            for (int i = tid; i < IH * IW; i += NT) {
+                const int r = i / IW, c = i - r * IW;
+                sI[r * IWP + c] -= mean;
             }
         }
         __syncthreads();
@@ -186,14 +215,14 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
         for (int task = tid; task < IH * NSH; task += NT) {
             const int r = task % IH, c0 = (task / IH) * MH;
             const float* src = sI + r * IWP + c0;
-            double w[MH + 2 * RG];
+            TC w[MH + 2 * RG];
 #pragma unroll
-            for (int i = 0; i < MH + 2 * RG; ++i) w[i] = (c0 + i < IW) ? static_cast<double>(src[i]) : 0.0;
+            for (int i = 0; i < MH + 2 * RG; ++i) w[i] = (c0 + i < IW) ? static_cast<TC>(src[i]) : TC(0);
 #pragma unroll
             for (int m = 0; m < MH; ++m) {
-                double acc = a.g[0] * w[m + RG];
+                TC acc = gw[0] * w[m + RG];
 #pragma unroll
-                for (int i = 1; i <= RG; ++i) acc = fma(a.g[i], w[m + RG - i] + w[m + RG + i], acc);
+                for (int i = 1; i <= RG; ++i) acc = fma(gw[i], w[m + RG - i] + w[m + RG + i], acc);
                 if (c0 + m < HC) sH[r * HC + c0 + m] = acc;
             }
         }
@@ -203,14 +232,14 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
         constexpr int NSV = (GH + MV - 1) / MV;
         for (int task = tid; task < HC * NSV; task += NT) {
             const int c = task % HC, r0 = (task / HC) * MV;
-            double w[MV + 2 * RG];
+            TC w[MV + 2 * RG];
 #pragma unroll
-            for (int i = 0; i < MV + 2 * RG; ++i) w[i] = (r0 + i < IH) ? sH[(r0 + i) * HC + c] : 0.0;
+            for (int i = 0; i < MV + 2 * RG; ++i) w[i] = (r0 + i < IH) ? sH[(r0 + i) * HC + c] : TC(0);
 #pragma unroll
             for (int m = 0; m < MV; ++m) {
-                double acc = a.g[0] * w[m + RG];
+                TC acc = gw[0] * w[m + RG];
 #pragma unroll
-                for (int i = 1; i <= RG; ++i) acc = fma(a.g[i], w[m + RG - i] + w[m + RG + i], acc);
+                for (int i = 1; i <= RG; ++i) acc = fma(gw[i], w[m + RG - i] + w[m + RG + i], acc);
                 if (r0 + m < GH) sG[(r0 + m) * HC + c] = acc;
             }
         }
@@ -220,35 +249,35 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
         constexpr int NSS = (KH + MS - 1) / MS;
         for (int task = tid; task < KW * NSS; task += NT) {
             const int c = task % KW, r0 = (task / KW) * MS;
-            double d2x[MS + 4], s5x[MS + 4], d1x[MS + 4];
+            TC d2x[MS + 4], s5x[MS + 4], d1x[MS + 4];
 #pragma unroll
             for (int i = 0; i < MS + 4; ++i) {
                 const int gr = r0 + i < GH ? r0 + i : GH - 1;
-                const double* g = sG + gr * HC + c;
-                const double gm2 = g[0], gm1 = g[1], g0 = g[2], gp1 = g[3], gp2 = g[4];
-                d2x[i] = (gm2 + gp2) - 2.0 * g0;
-                s5x[i] = (gm2 + gp2) + 4.0 * (gm1 + gp1) + 6.0 * g0;
-                d1x[i] = (gp2 - gm2) + 2.0 * (gp1 - gm1);
+                const TC* g = sG + gr * HC + c;
+                const TC gm2 = g[0], gm1 = g[1], g0 = g[2], gp1 = g[3], gp2 = g[4];
+                d2x[i] = (gm2 + gp2) - TC(2) * g0;
+                s5x[i] = (gm2 + gp2) + TC(4) * (gm1 + gp1) + TC(6) * g0;
+                d1x[i] = (gp2 - gm2) + TC(2) * (gp1 - gm1);
             }
 #pragma unroll
             for (int m = 0; m < MS; ++m) {
                 const int r = r0 + m;
                 if (r < KH && a.edge) {
                     // directed edges: Ix = S5_y D1_x G / 128, Iy = D1_y S5_x G / 128, m = -|grad I|
-                    const double ix = ((d1x[m] + d1x[m + 4]) + 4.0 * (d1x[m + 1] + d1x[m + 3]) + 6.0 * d1x[m + 2]) * (1.0 / 128.0);
-                    const double iy = ((s5x[m + 4] - s5x[m]) + 2.0 * (s5x[m + 3] - s5x[m + 1])) * (1.0 / 128.0);
-                    const double g = sqrt(ix * ix + iy * iy);
-                    const double k = -g;
+                    const TC ix = ((d1x[m] + d1x[m + 4]) + TC(4) * (d1x[m + 1] + d1x[m + 3]) + TC(6) * d1x[m + 2]) * TC(1.0 / 128.0);
+                    const TC iy = ((s5x[m + 4] - s5x[m]) + TC(2) * (s5x[m + 3] - s5x[m + 1])) * TC(1.0 / 128.0);
+                    const TC g = sqrt(ix * ix + iy * iy);
+                    const TC k = -g;
                     sK[r * KW + c] = k;
                     sQ[r * KW + c] = (DENSE || k < kthr) ? gradient_code(ix, iy, g) : 0u;
                 } else if (r < KH) {
-                    const double ixx = ((d2x[m] + d2x[m + 4]) + 4.0 * (d2x[m + 1] + d2x[m + 3]) + 6.0 * d2x[m + 2]) * (1.0 / 64.0);
-                    const double iyy = ((s5x[m] + s5x[m + 4]) - 2.0 * s5x[m + 2]) * (1.0 / 64.0);
-                    const double ixy = ((d1x[m + 4] - d1x[m]) + 2.0 * (d1x[m + 3] - d1x[m + 1])) * (1.0 / 64.0);
-                    const double tr = 0.5 * (ixx + iyy);
-                    const double h = 0.5 * (ixx - iyy);
-                    const double d = sqrt(h * h + ixy * ixy);
-                    const double k = tr - d;
+                    const TC ixx = ((d2x[m] + d2x[m + 4]) + TC(4) * (d2x[m + 1] + d2x[m + 3]) + TC(6) * d2x[m + 2]) * TC(1.0 / 64.0);
+                    const TC iyy = ((s5x[m] + s5x[m + 4]) - TC(2) * s5x[m + 2]) * TC(1.0 / 64.0);
+                    const TC ixy = ((d1x[m + 4] - d1x[m]) + TC(2) * (d1x[m + 3] - d1x[m + 1])) * TC(1.0 / 64.0);
+                    const TC tr = TC(0.5) * (ixx + iyy);
+                    const TC h = TC(0.5) * (ixx - iyy);
+                    const TC d = sqrt(h * h + ixy * ixy);
+                    const TC k = tr - d;
                     sK[r * KW + c] = k;
                     sQ[r * KW + c] = (DENSE || k < kthr) ? direction_code(h, ixy, d) : 0u;
                     if (DENSE && a.hess_dense && r >= 1 && r <= TH && c >= 1 && c <= TW) {
@@ -292,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
                 bool ridge = false;
                 if (x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2) {
                     const int o = (py + 1) * KW + px + 1;
-                    const double k = sK[o];
+                    const TC k = sK[o];
                     if (k < kthr) {
                         int nx, ny;
                         nms_offset(sQ[o], nx, ny);
@@ -339,8 +368,11 @@ __global__ __launch_bounds__(NT) void k_stencil(StencilArgs a) {
 
 template <typename TIN, int TW, int TH, int RG, bool DENSE>
 hipError_t launch_t(const StencilArgs& a, hipStream_t s) {
-    using SH = StencilShape<TW, TH, RG>;
-    hipLaunchKernelGGL((k_stencil<TIN, SH, DENSE>), dim3(a.total_tiles), dim3(NT), 0, s, a);
+    if (a.fp32) {
+        hipLaunchKernelGGL((k_stencil<TIN, StencilShape<TW, TH, RG, float>, DENSE>), dim3(a.total_tiles), dim3(NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_stencil<TIN, StencilShape<TW, TH, RG, double>, DENSE>), dim3(a.total_tiles), dim3(NT), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ class RdParams(ctypes.Structure):
                 ("vote_threshold", ctypes.c_int32), ("peak_fraction", ctypes.c_float),
                 ("sig_slope", ctypes.c_float), ("sig_icpt", ctypes.c_float),
                 ("annulus_halfwidth", ctypes.c_int32), ("min_fit_points", ctypes.c_int32),
-                ("measure", ctypes.c_int32), ("r_step", ctypes.c_int32)]
+                ("measure", ctypes.c_int32), ("r_step", ctypes.c_int32), ("curvature_fp32", ctypes.c_int32)]
 
 
 class RdRing(ctypes.Structure):
@@ -136,7 +136,7 @@ def make_params(d: dict) -> RdParams:
     return RdParams(float(d["sigma_smooth"]), float(d["k_threshold"]), int(d["r_min"]), int(d["r_max"]),
                     int(d["vote_threshold"]), float(d["peak_fraction"]), float(d["sig_slope"]),
                     float(d["sig_icpt"]), int(d["annulus_halfwidth"]), int(d["min_fit_points"]),
-                    int(d.get("measure", 0)), int(d.get("r_step", 1)))
+                    int(d.get("measure", 0)), int(d.get("r_step", 1)), int(d.get("curvature_fp32", 0)))
 
 
 def n_levels(d: dict) -> int:

@@ -62,6 +62,7 @@ def _p(**kw):
     (dict(r_min=4, r_step=4), False), (dict(r_min=5, r_step=4), True), (dict(r_min=1), False),
     (dict(r_min=2), True),
     (dict(r_min=100, r_max=124, r_step=3), True), (dict(r_min=100, r_max=124, r_step=4), False),
+    (dict(curvature_fp32=1), True), (dict(curvature_fp32=2), False), (dict(curvature_fp32=-1), False),
 ])
 def test_validate_params(kw, ok):
     lib = _ensure_built()
@@ -107,14 +108,14 @@ def test_create_without_gpu_reports_device_error():
     lib.rd_destroy(None)
 
 
-@pytest.mark.parametrize("gate,memory,c2,max_tracks", [
-    (0.0, 1, 72.0, 100), (-1.0, 1, 72.0, 100), (float("nan"), 1, 72.0, 100), (5.0, -1, 72.0, 100),
-    (5.0, 1, 0.0, 100), (5.0, 1, float("nan"), 100), (5.0, 1, 72.0, 0),
-    (5.0, 1, -72.0, 100), (5.0, 1, float("inf"), 100)])
-def test_linker_parameters_are_validated_before_device_work(gate, memory, c2, max_tracks):
+@pytest.mark.parametrize("gate,memory,c2,max_tracks,model", [
+    (0.0, 1, 72.0, 100, 0), (-1.0, 1, 72.0, 100, 0), (float("nan"), 1, 72.0, 100, 0), (5.0, -1, 72.0, 100, 0),
+    (5.0, 1, 0.0, 100, 0), (5.0, 1, float("nan"), 100, 0), (5.0, 1, 72.0, 0, 0),
+    (5.0, 1, -72.0, 100, 0), (5.0, 1, float("inf"), 100, 0), (5.0, 1, 72.0, 100, 2), (5.0, 1, 72.0, 100, -1)])
+def test_linker_parameters_are_validated_before_device_work(gate, memory, c2, max_tracks, model):
     lib = _ensure_built()
     h = ctypes.c_void_p()
-    p = N.RdLinkParams(gate, memory, 8.0, 0.0, c2)
+    p = N.RdLinkParams(gate, memory, 8.0, 0.0, c2, model)
     assert lib.rd_linker_create(ctypes.byref(p), max_tracks, 4, None, ctypes.byref(h)) == N.RD_E_INVALID
     offs = (ctypes.c_int32 * 2)(0, 0)
     assert lib.rd_link(None, None, offs, 1, None, None) == N.RD_E_INVALID
