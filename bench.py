@@ -75,7 +75,41 @@ def parse():
                     help="only copy a BYTES-sized device buffer 10 times (reference for HBM byte counters)")
     ap.add_argument("--lds-calibration", action="store_true",
                     help="only measure the LDS atomic-add rate (the vote step's ceiling)")
+    ap.add_argument("--vote-phases", action="store_true",
+                    help="only time the vote kernel's phases on the headline frame and a 2048^2 stream frame")
     return ap.parse_args()
+
+
+def vote_phases():
+    """Where the vote kernel's time goes: shader clocks per phase (summed over workgroups,
+    shares of their summed lifetimes, clocks per tile) on the headline c2 frame and on the first
+    2048^2 stream frame, from the library's phase-timed instance of the kernel; best of 3
+    calls by lifetime."""
+    import torch
+
+    from paper_1310_1371_amd import synth
+    from paper_1310_1371_amd.detector import Detector
+    det = Detector(max_width=2048, max_height=2048, max_peaks=16384)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count      # one vote workgroup per CU
+    st = synth.Stream(seed=4)
+    xs, ys, zs = st.trajectories(1)
+    f5 = torch.empty((2048, 2048), dtype=torch.int16, device="cuda")
+    st.render_device(xs[0], ys[0], zs[0], f5, torch.Generator(device="cuda").manual_seed(4))
+    f2 = synth.config2()
+    out = {}
+    for name, img, p in (("c2_1024_u16", torch.from_numpy(f2.image).cuda(), f2.params),
+                         ("c5_2048_u16_frame0", f5.view(torch.uint16), dict(synth.PARAMS_C5))):
+        det.detect(img, p)
+        best = min((det.profile_vote_phases(img, p) for _ in range(3)), key=lambda r: r["lifetime_sum"])
+        life = best["lifetime_sum"]
+        out[name] = {"tiles": best["tiles"],
+                     "clocks_per_tile": {k: v / best["tiles"] for k, v in best["phases"].items()},
+                     "share_of_lifetimes": {k: v / life for k, v in best["phases"].items()},
+                     "mean_tile_clocks": sum(best["phases"].values()) / best["tiles"],
+                     "workgroup_lifetime_clocks": {"max": best["lifetime_max"], "min": best["lifetime_min"],
+                                                   "mean": life / min(cus, best["tiles"])}}
+    det.close()
+    return out
 
 
 def lds_ceiling():
@@ -248,6 +282,9 @@ def main():
         return
     if args.lds_calibration:
         print(json.dumps({"lds_atomic_rate": lds_ceiling()}), flush=True)
+        return
+    if args.vote_phases:
+        print(json.dumps({"vote_phases": vote_phases()}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: frames are independent, so a batch would shard by frames "

@@ -225,6 +225,17 @@ rd_status rd_read_timing(rd_handle h, double* ms_total, int64_t* launches, int32
  * NULL) that launch's duration.  Allocates nothing; RD_E_DEVICE without a usable device. */
 rd_status rd_measure_lds_atomics(int32_t device, int32_t with_return, double* atomics_per_s, double* ms);
 
+/* Measurement only: one rd_detect of `frame`, launched directly (no graph), with a
+ * profiling instance of the vote kernel (steps 3-4) that reads the shader clock after the
+ * barrier ending each phase of each tile.  clocks[0..5] (host) receive the clocks summed over
+ * the workgroups of: tile set-up (queue, candidate bins, first histogram clear), ridge
+ * staging and the item sort, votes with hotspot listing, scores, the above-threshold list,
+ * and the 3x3x3 test with the next level chunk's clear; clocks[6] the workgroups' summed
+ * lifetimes, clocks[7] the tiles, clocks[8] and clocks[9] the longest and the shortest
+ * workgroup lifetime.  Same validation as rd_detect; RD_E_OVERFLOW as rd_detect. */
+#define RD_VOTE_PHASE_WORDS 10
+rd_status rd_profile_vote_phases(rd_handle h, const rd_frame* frame, const rd_params* params, uint64_t* clocks);
+
 /* ---- stage entry points (parity checks; same kernels as rd_detect) ------------------- */
 
 /* Step 1 only: k_- (float, H x W, row-major, device pointer) and the direction code of

@@ -335,6 +335,7 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
         RD_HIP(launch_tile_cost(ta, h->n_chunks, h->stream));
         va.tile_order = h->d_torder;
     }
+    if (h->phase_on) va.phase_clocks = h->d_phase;
     RD_HIP(launch_vote(va, h->tabs.lds, false, h->cus, h->stream));
     RD_TRY(mark(h, 2));
     RD_HIP(launch_fit(fit_args(h, p, nframes, rings, counts_out), FIT_GRID, h->stream));
@@ -695,6 +696,7 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_cmeta);
     (void)hipFree(h->d_eoff);
     (void)hipFree(h->d_tcost);
+    (void)hipFree(h->d_phase);
     (void)hipFree(h->d_torder);
     for (hipEvent_t& e : h->ev)
         if (e) (void)hipEventDestroy(e);
@@ -720,6 +722,35 @@ rd_status rd_detect(rd_handle h, const rd_frame* frame, const rd_params* params,
     record_stats(h, 1);
     if (h->h_counts[1]) return RD_E_OVERFLOW;
     return copy_rings(h, 0, out, capacity, n_rings);
+}
+
+static_assert(PH_COUNT + 4 == RD_VOTE_PHASE_WORDS, "the clock words the header declares");
+
+rd_status rd_profile_vote_phases(rd_handle h, const rd_frame* frame, const rd_params* params, uint64_t* clocks) {
+    if (!h || !clocks) return RD_E_INVALID;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_frame(h, frame));
+    RD_HIP(hipSetDevice(h->device));
+    if (!h->d_phase)
+        RD_HIP(hipMalloc(reinterpret_cast<void**>(&h->d_phase), (PH_COUNT + 4) * sizeof(unsigned long long)));
+    unsigned long long init[PH_COUNT + 4] = {};
+    init[PH_COUNT + 3] = ~0ull;                       // the minimum's start
+    RD_HIP(hipMemcpyAsync(h->d_phase, init, sizeof(init), hipMemcpyHostToDevice, h->stream));
+    // one detection, launched directly (no graph), with the profiling instance of the vote kernel
+    std::vector<rd_ring> rings(static_cast<size_t>(h->max_peaks));
+    int32_t n = 0;
+    const bool graph = h->tune.use_graph;
+    h->tune.use_graph = false;
+    h->phase_on = true;
+    const rd_status st = rd_detect(h, frame, params, rings.data(), h->max_peaks, &n);
+    h->phase_on = false;
+    h->tune.use_graph = graph;
+    if (st != RD_OK && st != RD_E_TRUNCATED) return st;
+    unsigned long long out[PH_COUNT + 4];
+    RD_HIP(hipMemcpyAsync(out, h->d_phase, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+    RD_HIP(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < PH_COUNT + 4; ++i) clocks[i] = out[i];
+    return RD_OK;
 }
 
 rd_status rd_detect_batch(rd_handle h, const rd_frame* frames, int32_t n, const rd_params* params, rd_ring* out,

@@ -106,6 +106,8 @@ struct rd_ctx {
     // tile order of the vote kernel (launches of up to ORDER_MAX vote tiles): per-tile cost
     // estimates (zero between launches) and the order
     uint32_t* d_tcost = nullptr;
+    unsigned long long* d_phase = nullptr;   // rd_profile_vote_phases: the clocks (allocated on first use)
+    bool phase_on = false;
     uint32_t* d_torder = nullptr;
     int n_chunks = 0;                   // COST_CHUNK-bin chunks of the current launch's frames
     // pinned host memory; rings and counts are written by the fit kernel through mappings

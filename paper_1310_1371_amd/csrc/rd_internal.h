@@ -101,7 +101,12 @@ struct VoteArgs {
     uint32_t* acc_dump;          // stage mode (single frame): dense [L][H][W]
     uint64_t* score_dump;
     const uint32_t* tile_order;  // [total_vtiles] the queue's tiles, estimated costliest first (may be null)
+    unsigned long long* phase_clocks;  // profiling instance: [PH_COUNT + 4] (null: the plain kernel)
 };
+
+// Phases of the vote kernel's profiling instance (clocks summed over workgroups), then the
+// workgroups' summed lifetime, the tiles, the longest and the shortest lifetime
+enum { PH_SETUP = 0, PH_STAGE, PH_VOTE, PH_SCORE, PH_STRONG, PH_PEAK, PH_COUNT };
 
 // The tile-cost pass: every (ridge, sign) casts its vote at one level in COST_STEP into a
 // per-tile counter (the tile that holds the vote), an estimate of the tiles' vote work; a

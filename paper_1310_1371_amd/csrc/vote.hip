@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t dot2_u16(uint32_t a, uint32_t b, uint32_t c)
 // One block per CU walks the vote tiles of the launch.  For each tile it stages the ridge
 // records of every bin that can reach the tile at any radius in LDS once, then runs the
 // level chunks over them.
-template <int T, bool DUMP>
+template <int T, bool DUMP, bool PHASES = false>
 __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     constexpr int SR = T + 2, SR2 = SR * SR;
     static_assert(SR2 <= HCAP, "per-level fallback needs a whole score region in the list");
@@ -134,6 +134,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int L = a.nlevels;
+    // phase clocks (the profiling instance only): thread 0 reads the shader clock after the
+    // barrier that ends each phase, so each span is the workgroup's
+    unsigned long long ph_acc[PH_COUNT] = {}, ph_last = 0, ph_start = 0;
+    int ph_tiles = 0;
+    if (PHASES && tid == 0) ph_start = ph_last = __builtin_readcyclecounter();
+    auto stamp = [&](int ph) {
+        if (PHASES && tid == 0) {
+            const unsigned long long now = __builtin_readcyclecounter();
+            ph_acc[ph] += now - ph_last;
+            ph_last = now;
+        }
+    };
     for (int i = tid; i < L * (K_MAX + 1); i += NT) {
         const int li = i / (K_MAX + 1), d = i - li * (K_MAX + 1);
         sWt[li][d] = static_cast<uint16_t>(a.wtab[i]);
@@ -246,6 +258,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         };
         prepare(0);
         __syncthreads();
+        stamp(PH_SETUP);
+        if (PHASES) ++ph_tiles;
 
         for (int c = 0; c < a.nchunks; ++c) {
             const int rc0 = sChunk[c], rc1 = sChunk[c + 1];
@@ -376,6 +390,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         if (key != 255u) sOrd[atomicAdd(&sKey[key], 1u)] = static_cast<uint16_t>(it);
                     }
                     __syncthreads();
+                    stamp(PH_STAGE);
                 }
                 // votes: each staged (ridge, sign) item over its level range clipped to this
                 // chunk, split between two lanes (half of the levels each), which spreads the
@@ -448,6 +463,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     }
                 }
                 __syncthreads();
+                stamp(PH_VOTE);
                 if (pc + 1 >= sNPieces) break;
             }
 
@@ -598,6 +614,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     if (acc) atomicAdd(&sHS[h], acc);
                 }
                 __syncthreads();
+                stamp(PH_SCORE);
                 for (int h = tid; h < nh; h += NT) {
                     const uint32_t e = sHot[h];
                     const int li = e >> 16, sidx = e & 0xffff;
@@ -619,6 +636,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 }
                 }
                 __syncthreads();
+                stamp(PH_STRONG);
                 if (first) {
                     const uint32_t ns_all = sNs;
                     if (tid == 0) {
@@ -747,7 +765,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             if (windows && !per_level) __syncthreads();       // the table in the histogram is done
             if (c + 1 < a.nchunks) prepare(c + 1);
             __syncthreads();
+            stamp(PH_PEAK);
         }
+    }
+    if (PHASES && tid == 0) {
+        // per workgroup: each phase's clocks, its lifetime, its tiles; the longest and the
+        // shortest lifetime over the workgroups
+        const unsigned long long life = __builtin_readcyclecounter() - ph_start;
+        for (int i = 0; i < PH_COUNT; ++i) atomicAdd(&a.phase_clocks[i], ph_acc[i]);
+        atomicAdd(&a.phase_clocks[PH_COUNT], life);
+        atomicAdd(&a.phase_clocks[PH_COUNT + 1], static_cast<unsigned long long>(ph_tiles));
+        atomicMax(&a.phase_clocks[PH_COUNT + 2], life);
+        atomicMin(&a.phase_clocks[PH_COUNT + 3], life);
     }
     if (a.stats) {
         unsigned long long v = st_votes, tp = st_taps;
@@ -960,6 +989,9 @@ hipError_t vote_prepare() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
 }
@@ -971,6 +1003,8 @@ hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hip
     if (blocks > a.total_vtiles) blocks = a.total_vtiles;   // persistent blocks take tiles from the queue
     if (dump)
         hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(blocks), dim3(NT), lds, s, a);
+    else if (a.phase_clocks)
+        hipLaunchKernelGGL((k_vote<VOTE_TILE, false, true>), dim3(blocks), dim3(NT), lds, s, a);
     else
         hipLaunchKernelGGL((k_vote<VOTE_TILE, false>), dim3(blocks), dim3(NT), lds, s, a);
     return hipGetLastError();

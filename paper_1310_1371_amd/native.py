@@ -92,6 +92,7 @@ SIGNATURES = {
     "rd_hessian_backward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(RdParams), _vp]),
     "rd_fit_loss": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp]),
     "rd_fit_loss_backward": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp, _vp]),
+    "rd_profile_vote_phases": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp]),
     "rd_refine": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _vp, _vp, _i64, ctypes.c_double, _i32, ctypes.c_double,
                                  _vp, _vp, _vp]),
     "rd_linker_create": (ctypes.c_int, [_P(RdLinkParams), _i32, _i32, _vp, _P(_vp)]),
