@@ -582,32 +582,31 @@ def radius_step(det, frame, f, args, np, torch):
 
 
 def differentiable(det, args, np, torch, synth):
-    from paper_1310_1371_amd.autograd import ring_fit_loss, soft_accumulator
+    from paper_1310_1371_amd.autograd import ring_fit_loss_batch, soft_accumulator_batch
 
     fs = synth.config4(seed=3, n_frames=args.diff_frames)
     p = fs[0].params
     s = 1.5
     imgs = [torch.from_numpy(fr.image).cuda() for fr in fs]
+    X = torch.stack(imgs)                       # the frames as one [F, H, W] tensor in HBM
     L = p["r_max"] - p["r_min"] + 3
     G = torch.randn((L, 1024, 1024), device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
+    Gb = G.expand(len(fs), -1, -1, -1).contiguous()     # the upstream gradient of every frame's accumulator
 
     def step():
+        # detection, then the soft accumulator and the ring losses of all frames with their
+        # gradients (one library call per stage for the whole batch), then 20 LM steps per ring
         res = det.detect_batch(imgs, p)
-        th0_list, fo = [], []
-        grads = []
-        for i, (img, rings) in enumerate(zip(imgs, res)):
-            th0 = torch.from_numpy(np.stack([rings["cx"], rings["cy"], rings["r"]], 1).astype(np.float64)).cuda()
-            x = img.clone().requires_grad_(True)
-            acc = soft_accumulator(x, det, p)
-            theta = th0.clone().requires_grad_(True)
-            loss = ring_fit_loss(x, theta, th0, det, s)
-            torch.autograd.backward([loss.sum(), acc], [None, G])
-            grads.append((x.grad, theta.grad))
-            th0_list.append(th0)
-            fo.append(torch.full((th0.shape[0],), i, dtype=torch.int32, device="cuda"))
-        th0_all = torch.cat(th0_list)
-        theta, lm_loss = det.refine(imgs, th0_all, s, iters=20, frame_of=torch.cat(fo))
-        return res, th0_all, theta, grads
+        th0_all = torch.from_numpy(np.concatenate([np.stack([r["cx"], r["cy"], r["r"]], 1) for r in res])
+                                   .astype(np.float64)).cuda()
+        fo = torch.from_numpy(np.concatenate([np.full(len(r), i) for i, r in enumerate(res)]).astype(np.int32)).cuda()
+        x = X.clone().requires_grad_(True)
+        acc = soft_accumulator_batch(x, det, p)
+        theta = th0_all.clone().requires_grad_(True)
+        loss = ring_fit_loss_batch(x, theta, th0_all, fo, det, s)
+        torch.autograd.backward([loss.sum(), acc], [None, Gb])
+        theta_ref, lm_loss = det.refine(imgs, th0_all, s, iters=20, frame_of=fo)
+        return res, th0_all, theta_ref, (x.grad, theta.grad)
 
     res, th0_all, theta, _ = step()
     torch.cuda.synchronize()
@@ -649,7 +648,7 @@ def differentiable(det, args, np, torch, synth):
                                 "refined": {"cx": float(err_r[:, 0].mean()), "cy": float(err_r[:, 1].mean()),
                                             "r": float(err_r[:, 2].mean())}},
             "workload": "16 f32 1024^2 frames, 300 rings each: batched detection, soft accumulator + ring loss "
-                        "forward/backward per frame, 20 LM steps per detected ring"}
+                        "forward/backward over the batch (one library call per stage), 20 LM steps per detected ring"}
 
 
 def stream(det, args, np, torch, synth):

@@ -411,6 +411,51 @@ rd_status rd_fit_loss_backward(rd_handle h, const rd_frame* frame, const double*
                                const double* grad_loss_dev, float* grad_img_dev,
                                double* grad_theta_dev);
 
+/* ---- the same calls over a batch of frames (one call each; the kernels are the
+ * single-frame ones, enqueued frame after frame with no host synchronisation between them
+ * except where a single-frame call has one).  Per-frame arrays lie back to back: ridges at
+ * host offsets[i] .. offsets[i + 1] (nframes + 1 entries, offsets[0] = 0), soft
+ * accumulators float32 [L][height_i][width_i] one after another, image gradients float32
+ * [height_i][width_i] one after another.  widths / heights: host arrays of nframes. */
+
+/* rd_soft_ridges over nframes frames into one list; offsets (host, nframes + 1) receive the
+ * frames' starts.  RD_E_TRUNCATED if the total exceeds capacity (offsets then hold every
+ * frame's count; ridges and Hessians are written up to the first frame that did not fit). */
+rd_status rd_soft_ridges_batch(rd_handle h, const rd_frame* frames, int32_t nframes, const rd_params* params,
+                               int32_t* xy_dev, double* hess_dev, int64_t capacity, int64_t* offsets);
+
+/* rd_soft_forward per frame; statuses as rd_soft_forward, over the whole batch. */
+rd_status rd_soft_forward_batch(rd_handle h, const int32_t* xy_dev, const double* hess_dev,
+                                const int64_t* offsets, const int32_t* widths, const int32_t* heights,
+                                int32_t nframes, const rd_params* params, float* acc_dev);
+
+/* rd_soft_backward per frame; *n_isotropic (may be NULL: then enqueued) sums the frames'. */
+rd_status rd_soft_backward_batch(rd_handle h, const int32_t* xy_dev, const double* hess_dev,
+                                 const int64_t* offsets, const int32_t* widths, const int32_t* heights,
+                                 int32_t nframes, const rd_params* params, const float* grad_acc_dev,
+                                 double* grad_hess_dev, int64_t* n_isotropic);
+
+/* rd_hessian_backward per frame, ADDING into each frame's gradient plane.  Enqueued. */
+rd_status rd_hessian_backward_batch(rd_handle h, const int32_t* xy_dev, const double* grad_hess_dev,
+                                    const int64_t* offsets, const int32_t* widths, const int32_t* heights,
+                                    int32_t nframes, const rd_params* params, float* grad_img_dev);
+
+/* rd_fit_loss of m rings over up to 64 device frames, ring j on frame frame_of_dev[j]
+ * (int32, device; may be NULL when nframes == 1); rings with a frame index outside
+ * [0, nframes) get NaN.  Enqueued. */
+rd_status rd_fit_loss_batch(rd_handle h, const rd_frame* frames, int32_t nframes, const int32_t* frame_of_dev,
+                            const double* theta_dev, const double* theta0_dev, int64_t m, double s,
+                            double* loss_dev, double* ab_dev);
+
+/* rd_fit_loss_backward over up to 64 frames: d/dI ADDED into the frames' gradient planes
+ * (grad_img_dev may be NULL), d/dtheta per ring (NaN for rings outside the frames).
+ * Enqueued. */
+rd_status rd_fit_loss_backward_batch(rd_handle h, const rd_frame* frames, int32_t nframes,
+                                     const int32_t* frame_of_dev, const double* theta_dev,
+                                     const double* theta0_dev, int64_t m, double s,
+                                     const double* grad_loss_dev, float* grad_img_dev,
+                                     double* grad_theta_dev);
+
 /* Levenberg-Marquardt refinement of m rings over up to 64 device frames (frame_of_dev[j]
  * = frame of ring j, int32; may be NULL when nframes == 1): from theta0_dev, at most
  * `iters` steps of (J^T J + lam diag J^T J) d = -J^T e on the residuals of L_j with (A, B)

@@ -141,20 +141,28 @@ rd_status rd_soft_ridges(rd_handle h, const rd_frame* frame, const rd_params* pa
     return RD_OK;
 }
 
-rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess_dev, int64_t n, int32_t width,
-                          int32_t height, const rd_params* params, float* acc_dev) {
-    if (!h || !params || !acc_dev || n < 0 || (n > 0 && (!xy_dev || !hess_dev))) return RD_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// The parameter checks the soft accumulator and its adjoints share.
+rd_status soft_params_ok(const rd_params* params, bool levels) {
     RD_TRY(rd_validate_params(params));
     if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
     if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
-    if (param_rstep(*params) != 1) return RD_E_INVALID;             // levels in steps of one pixel
-    RD_TRY(check_dims(h, width, height));
-    RD_HIP(hipSetDevice(h->device));
-    SoftState* s = nullptr;
-    RD_TRY(soft_state(h, &s));
+    if (levels && param_rstep(*params) != 1) return RD_E_INVALID;   // levels in steps of one pixel
+    return RD_OK;
+}
+
+int64_t acc_elems(const rd_params& p, int W, int H) {
+    return static_cast<int64_t>(p.r_max - p.r_min + 3) * W * H;
+}
+
+// Enqueues the soft accumulator of one frame's ridges (flags are cleared and read by the caller).
+rd_status soft_forward_one(rd_ctx* h, SoftState* s, const int32_t* xy_dev, const double* hess_dev, int64_t n,
+                           int32_t width, int32_t height, const rd_params* params, float* acc_dev) {
     const int nbx = (width + BIN - 1) / BIN, nby = (height + BIN - 1) / BIN;
     RD_HIP(launch_fill_u32(s->bin_count, static_cast<int64_t>(nbx) * nby, h->stream));
-    RD_HIP(launch_fill_u32(s->flags, 2, h->stream));
     SoftBinArgs b{};
     b.xy = xy_dev;
     b.hess = hess_dev;
@@ -183,26 +191,41 @@ rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess
     f.L = params->r_max - params->r_min + 3;
     f.acc = acc_dev;
     RD_HIP(launch_soft_forward(f, h->stream));
+    return RD_OK;
+}
+
+rd_status soft_flags_status(rd_ctx* h, SoftState* s) {
     RD_TRY(read_flags(h, s));
     if (s->h_flags[0] & 2u) return RD_E_INVALID;
     if (s->h_flags[0] & 1u) return RD_E_OVERFLOW;
     return RD_OK;
 }
 
-rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hess_dev, int64_t n, int32_t width,
-                           int32_t height, const rd_params* params, const float* grad_acc_dev, double* grad_hess_dev,
-                           int64_t* n_isotropic) {
-    if (!h || !params || n < 0 || (n > 0 && (!xy_dev || !hess_dev || !grad_acc_dev || !grad_hess_dev)))
-        return RD_E_INVALID;
-    RD_TRY(rd_validate_params(params));
-    if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
-    if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
-    if (param_rstep(*params) != 1) return RD_E_INVALID;             // levels in steps of one pixel
+}  // namespace
+
+extern "C" {
+
+rd_status rd_soft_forward(rd_handle h, const int32_t* xy_dev, const double* hess_dev, int64_t n, int32_t width,
+                          int32_t height, const rd_params* params, float* acc_dev) {
+    if (!h || !params || !acc_dev || n < 0 || (n > 0 && (!xy_dev || !hess_dev))) return RD_E_INVALID;
+    RD_TRY(soft_params_ok(params, true));
     RD_TRY(check_dims(h, width, height));
     RD_HIP(hipSetDevice(h->device));
     SoftState* s = nullptr;
     RD_TRY(soft_state(h, &s));
-    if (n_isotropic) RD_HIP(launch_fill_u32(s->flags + 1, 1, h->stream));
+    RD_HIP(launch_fill_u32(s->flags, 2, h->stream));
+    RD_TRY(soft_forward_one(h, s, xy_dev, hess_dev, n, width, height, params, acc_dev));
+    return soft_flags_status(h, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Enqueues the soft accumulator's vector-Jacobian product for one frame's ridges.
+rd_status soft_backward_one(rd_ctx* h, const int32_t* xy_dev, const double* hess_dev, int64_t n, int32_t width,
+                            int32_t height, const rd_params* params, const float* grad_acc_dev, double* grad_hess_dev,
+                            uint32_t* n_iso) {
     SoftBwdArgs a{};
     a.xy = xy_dev;
     a.hess = hess_dev;
@@ -213,25 +236,14 @@ rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hes
     a.L = params->r_max - params->r_min + 3;
     a.grad_acc = grad_acc_dev;
     a.grad_hess = grad_hess_dev;
-    a.n_iso = n_isotropic ? s->flags + 1 : nullptr;
+    a.n_iso = n_iso;
     RD_HIP(launch_soft_backward(a, h->stream));
-    if (n_isotropic) {
-        RD_TRY(read_flags(h, s));
-        *n_isotropic = s->h_flags[1];
-    }
     return RD_OK;
 }
 
-rd_status rd_hessian_backward(rd_handle h, const int32_t* xy_dev, const double* grad_hess_dev, int64_t n,
-                              int32_t width, int32_t height, const rd_params* params, float* grad_img_dev) {
-    if (!h || !params || !grad_img_dev || n < 0 || (n > 0 && (!xy_dev || !grad_hess_dev))) return RD_E_INVALID;
-    RD_TRY(rd_validate_params(params));
-    if (params->measure != RD_MEASURE_RIDGE) return RD_E_INVALID;   // defined for directed ridges
-    if (params->curvature_fp32) return RD_E_INVALID;                 // the Hessian in float64
-    RD_TRY(check_dims(h, width, height));
-    RD_HIP(hipSetDevice(h->device));
-    SoftState* s = nullptr;
-    RD_TRY(soft_state(h, &s));
+// Enqueues the Hessian adjoint of one frame (adds into grad_img_dev, [height][width]).
+rd_status hessian_backward_one(rd_ctx* h, SoftState* s, const int32_t* xy_dev, const double* grad_hess_dev, int64_t n,
+                               int32_t width, int32_t height, const rd_params* params, float* grad_img_dev) {
     const int64_t npx = static_cast<int64_t>(width) * height;
     float* P = s->planes;               // gradient w.r.t. Ixx, Iyy, Ixy
     float* T = s->planes + 3 * npx;     // after the transposed y correlations
@@ -292,6 +304,189 @@ rd_status rd_hessian_backward(rd_handle h, const int32_t* xy_dev, const double* 
     g.out[0] = grad_img_dev;
     g.accumulate = 1;
     RD_HIP(launch_adj_pass(g, 0, h->stream));
+    return RD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rd_status rd_soft_backward(rd_handle h, const int32_t* xy_dev, const double* hess_dev, int64_t n, int32_t width,
+                           int32_t height, const rd_params* params, const float* grad_acc_dev, double* grad_hess_dev,
+                           int64_t* n_isotropic) {
+    if (!h || !params || n < 0 || (n > 0 && (!xy_dev || !hess_dev || !grad_acc_dev || !grad_hess_dev)))
+        return RD_E_INVALID;
+    RD_TRY(soft_params_ok(params, true));
+    RD_TRY(check_dims(h, width, height));
+    RD_HIP(hipSetDevice(h->device));
+    SoftState* s = nullptr;
+    RD_TRY(soft_state(h, &s));
+    if (n_isotropic) RD_HIP(launch_fill_u32(s->flags + 1, 1, h->stream));
+    RD_TRY(soft_backward_one(h, xy_dev, hess_dev, n, width, height, params, grad_acc_dev, grad_hess_dev,
+                             n_isotropic ? s->flags + 1 : nullptr));
+    if (n_isotropic) {
+        RD_TRY(read_flags(h, s));
+        *n_isotropic = s->h_flags[1];
+    }
+    return RD_OK;
+}
+
+rd_status rd_hessian_backward(rd_handle h, const int32_t* xy_dev, const double* grad_hess_dev, int64_t n,
+                              int32_t width, int32_t height, const rd_params* params, float* grad_img_dev) {
+    if (!h || !params || !grad_img_dev || n < 0 || (n > 0 && (!xy_dev || !grad_hess_dev))) return RD_E_INVALID;
+    RD_TRY(soft_params_ok(params, false));
+    RD_TRY(check_dims(h, width, height));
+    RD_HIP(hipSetDevice(h->device));
+    SoftState* s = nullptr;
+    RD_TRY(soft_state(h, &s));
+    return hessian_backward_one(h, s, xy_dev, grad_hess_dev, n, width, height, params, grad_img_dev);
+}
+
+// ---- batches of frames: the same kernels per frame, enqueued back to back with no host
+// synchronisation between frames
+
+rd_status rd_soft_ridges_batch(rd_handle h, const rd_frame* frames, int32_t nframes, const rd_params* params,
+                               int32_t* xy_dev, double* hess_dev, int64_t capacity, int64_t* offsets) {
+    if (!h || !params || !frames || !offsets || nframes < 1 || capacity < 0 || (capacity > 0 && !xy_dev))
+        return RD_E_INVALID;
+    offsets[0] = 0;
+    bool truncated = false;
+    for (int i = 0; i < nframes; ++i) {
+        const int64_t off = offsets[i];
+        const int64_t room = truncated ? 0 : (capacity > off ? capacity - off : 0);
+        int64_t n = 0;
+        const rd_status st = rd_soft_ridges(h, &frames[i], params, room ? xy_dev + 2 * off : nullptr,
+                                            room && hess_dev ? hess_dev + 3 * off : nullptr, room, &n);
+        if (st == RD_E_TRUNCATED) truncated = true;
+        else if (st != RD_OK) return st;
+        offsets[i + 1] = off + n;
+    }
+    return truncated ? RD_E_TRUNCATED : RD_OK;
+}
+
+namespace {
+
+// Checks a batch's ridge offsets and sizes (host arrays).
+rd_status batch_dims_ok(rd_ctx* h, const int64_t* offsets, const int32_t* widths, const int32_t* heights,
+                        int32_t nframes) {
+    if (!offsets || !widths || !heights || nframes < 1 || offsets[0] != 0) return RD_E_INVALID;
+    for (int i = 0; i < nframes; ++i) {
+        if (offsets[i + 1] < offsets[i]) return RD_E_INVALID;
+        RD_TRY(check_dims(h, widths[i], heights[i]));
+    }
+    return RD_OK;
+}
+
+}  // namespace
+
+rd_status rd_soft_forward_batch(rd_handle h, const int32_t* xy_dev, const double* hess_dev, const int64_t* offsets,
+                                const int32_t* widths, const int32_t* heights, int32_t nframes, const rd_params* params,
+                                float* acc_dev) {
+    if (!h || !params || !acc_dev) return RD_E_INVALID;
+    RD_TRY(soft_params_ok(params, true));
+    RD_TRY(batch_dims_ok(h, offsets, widths, heights, nframes));
+    if (offsets[nframes] > 0 && (!xy_dev || !hess_dev)) return RD_E_INVALID;
+    RD_HIP(hipSetDevice(h->device));
+    SoftState* s = nullptr;
+    RD_TRY(soft_state(h, &s));
+    RD_HIP(launch_fill_u32(s->flags, 2, h->stream));
+    int64_t aoff = 0;
+    for (int i = 0; i < nframes; ++i) {
+        const int64_t o = offsets[i];
+        RD_TRY(soft_forward_one(h, s, xy_dev + 2 * o, hess_dev + 3 * o, offsets[i + 1] - o, widths[i], heights[i],
+                                params, acc_dev + aoff));
+        aoff += acc_elems(*params, widths[i], heights[i]);
+    }
+    return soft_flags_status(h, s);
+}
+
+rd_status rd_soft_backward_batch(rd_handle h, const int32_t* xy_dev, const double* hess_dev, const int64_t* offsets,
+                                 const int32_t* widths, const int32_t* heights, int32_t nframes,
+                                 const rd_params* params, const float* grad_acc_dev, double* grad_hess_dev,
+                                 int64_t* n_isotropic) {
+    if (!h || !params || !grad_acc_dev) return RD_E_INVALID;
+    RD_TRY(soft_params_ok(params, true));
+    RD_TRY(batch_dims_ok(h, offsets, widths, heights, nframes));
+    if (offsets[nframes] > 0 && (!xy_dev || !hess_dev || !grad_hess_dev)) return RD_E_INVALID;
+    RD_HIP(hipSetDevice(h->device));
+    SoftState* s = nullptr;
+    RD_TRY(soft_state(h, &s));
+    if (n_isotropic) RD_HIP(launch_fill_u32(s->flags + 1, 1, h->stream));
+    int64_t aoff = 0;
+    for (int i = 0; i < nframes; ++i) {
+        const int64_t o = offsets[i];
+        RD_TRY(soft_backward_one(h, xy_dev + 2 * o, hess_dev + 3 * o, offsets[i + 1] - o, widths[i], heights[i],
+                                 params, grad_acc_dev + aoff, grad_hess_dev + 3 * o,
+                                 n_isotropic ? s->flags + 1 : nullptr));
+        aoff += acc_elems(*params, widths[i], heights[i]);
+    }
+    if (n_isotropic) {
+        RD_TRY(read_flags(h, s));
+        *n_isotropic = s->h_flags[1];
+    }
+    return RD_OK;
+}
+
+rd_status rd_hessian_backward_batch(rd_handle h, const int32_t* xy_dev, const double* grad_hess_dev,
+                                    const int64_t* offsets, const int32_t* widths, const int32_t* heights,
+                                    int32_t nframes, const rd_params* params, float* grad_img_dev) {
+    if (!h || !params || !grad_img_dev) return RD_E_INVALID;
+    RD_TRY(soft_params_ok(params, false));
+    RD_TRY(batch_dims_ok(h, offsets, widths, heights, nframes));
+    if (offsets[nframes] > 0 && (!xy_dev || !grad_hess_dev)) return RD_E_INVALID;
+    RD_HIP(hipSetDevice(h->device));
+    SoftState* s = nullptr;
+    RD_TRY(soft_state(h, &s));
+    int64_t poff = 0;
+    for (int i = 0; i < nframes; ++i) {
+        const int64_t o = offsets[i];
+        RD_TRY(hessian_backward_one(h, s, xy_dev + 2 * o, grad_hess_dev + 3 * o, offsets[i + 1] - o, widths[i],
+                                    heights[i], params, grad_img_dev + poff));
+        poff += static_cast<int64_t>(widths[i]) * heights[i];
+    }
+    return RD_OK;
+}
+
+rd_status rd_fit_loss_batch(rd_handle h, const rd_frame* frames, int32_t nframes, const int32_t* frame_of_dev,
+                            const double* theta_dev, const double* theta0_dev, int64_t m, double s, double* loss_dev,
+                            double* ab_dev) {
+    if (!h || m < 0 || (m > 0 && (!theta_dev || !theta0_dev || !loss_dev))) return RD_E_INVALID;
+    if (nframes > 1 && m > 0 && !frame_of_dev) return RD_E_INVALID;
+    RingArgs a;
+    RD_TRY(ring_args(h, frames, nframes, s, &a));
+    RD_HIP(hipSetDevice(h->device));
+    a.frame_of = frame_of_dev;
+    a.m = m;
+    a.theta = theta_dev;
+    a.theta0 = theta0_dev;
+    a.loss = loss_dev;
+    a.ab = ab_dev;
+    RD_HIP(launch_fit_loss(a, false, h->stream));
+    return RD_OK;
+}
+
+rd_status rd_fit_loss_backward_batch(rd_handle h, const rd_frame* frames, int32_t nframes, const int32_t* frame_of_dev,
+                                     const double* theta_dev, const double* theta0_dev, int64_t m, double s,
+                                     const double* grad_loss_dev, float* grad_img_dev, double* grad_theta_dev) {
+    if (!h || m < 0 || (m > 0 && (!theta_dev || !theta0_dev || !grad_loss_dev || !grad_theta_dev)))
+        return RD_E_INVALID;
+    if (nframes > 1 && m > 0 && !frame_of_dev) return RD_E_INVALID;
+    RingArgs a;
+    RD_TRY(ring_args(h, frames, nframes, s, &a));
+    RD_HIP(hipSetDevice(h->device));
+    int64_t poff = 0;
+    for (int i = 0; i < nframes; ++i) {        // the frames' gradient planes, back to back
+        a.frames[i].grad_off = poff;
+        poff += static_cast<int64_t>(frames[i].width) * frames[i].height;
+    }
+    a.frame_of = frame_of_dev;
+    a.m = m;
+    a.theta = theta_dev;
+    a.theta0 = theta0_dev;
+    a.grad_loss = grad_loss_dev;
+    a.grad_img = grad_img_dev;
+    a.grad_theta = grad_theta_dev;
+    RD_HIP(launch_fit_loss(a, true, h->stream));
     return RD_OK;
 }
 

@@ -285,7 +285,8 @@ __global__ __launch_bounds__(NT) void k_fit_loss(RingArgs a, int backward) {
         for_members(f, w, M, [&](int x, int y, double I) {
             const Prof p = profile(th, inv2s2, invs2, x, y);
             const double e = I - B - A * p.g;
-            if (a.grad_img) atomicAdd(&a.grad_img[static_cast<int64_t>(y) * f.W + x], static_cast<float>(gl * 2.0 * e));
+            if (a.grad_img)
+                atomicAdd(&a.grad_img[f.grad_off + static_cast<int64_t>(y) * f.W + x], static_cast<float>(gl * 2.0 * e));
             double d[3];
             profile_grad(p, th, x, y, d);
             const double c = -2.0 * A * e;

@@ -284,6 +284,7 @@ struct RingFrame {
     const void* img;
     int64_t pitch;           // bytes
     int32_t W, H, dtype, pad;
+    int64_t grad_off;        // backward: first element of this frame's [H][W] plane in grad_img
 };
 
 constexpr int RING_FRAMES_MAX = 64;   // frames of one ring-profile launch (kernel arguments)
@@ -298,7 +299,7 @@ struct RingArgs {
     double* loss;            // [m]
     double* ab;              // [m][2] A, B (may be null)
     const double* grad_loss; // backward: [m] upstream gradient
-    float* grad_img;         // backward: [H][W] of frame 0, added into (may be null)
+    float* grad_img;         // backward: the frames' [H][W] planes from RingFrame.grad_off, added into (may be null)
     double* grad_theta;      // backward: [m][3]
     int32_t iters;           // refinement steps, at most
     double tol;              // a step whose update is within tol in every component is the last

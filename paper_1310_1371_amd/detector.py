@@ -359,6 +359,120 @@ class Detector:
                                               height, ctypes.byref(p), grad_img.data_ptr()), "rd_hessian_backward")
         return grad_img
 
+    # ---- the differentiable calls over a batch of frames (one library call each)
+    def soft_ridges_batch(self, frames, params: dict, capacity: int | None = None):
+        """Ridge sets of several device frames as one list: xy int32 [N, 2], hess float64
+        [N, 3], and the frames' offsets into it (numpy int64 [nframes + 1])."""
+        arr = self._frame_array(frames)
+        n = len(frames)
+        if capacity is None:
+            capacity = sum(int(a.width) * int(a.height) for a in arr) // 4
+        xy = torch.empty((capacity, 2), dtype=torch.int32, device=self._dev())
+        hess = torch.empty((capacity, 3), dtype=torch.float64, device=self._dev())
+        offs = np.zeros(n + 1, dtype=np.int64)
+        p = N.make_params(params)
+        N.check(self._lib.rd_soft_ridges_batch(self._h, arr, n, ctypes.byref(p), xy.data_ptr(), hess.data_ptr(),
+                                               capacity, offs.ctypes.data), "rd_soft_ridges_batch")
+        return xy[:int(offs[-1])], hess[:int(offs[-1])], offs
+
+    @staticmethod
+    def _sizes(sizes):
+        w = np.ascontiguousarray([int(s[0]) for s in sizes], dtype=np.int32)
+        h = np.ascontiguousarray([int(s[1]) for s in sizes], dtype=np.int32)
+        return w, h
+
+    def soft_forward_batch(self, xy, hess, offsets, sizes, params: dict) -> torch.Tensor:
+        """Soft accumulators of a batch (sizes: (width, height) per frame), back to back as one
+        float32 tensor; [nframes, L, H, W] when every frame has one size."""
+        xy, hess = self._soft_inputs(xy, hess)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        w, h = self._sizes(sizes)
+        L = int(params["r_max"]) - int(params["r_min"]) + 3
+        acc = torch.empty(int((L * w.astype(np.int64) * h).sum()), dtype=torch.float32, device=self._dev())
+        p = N.make_params(params)
+        N.check(self._lib.rd_soft_forward_batch(self._h, xy.data_ptr(), hess.data_ptr(), offs.ctypes.data,
+                                                w.ctypes.data, h.ctypes.data, len(w), ctypes.byref(p),
+                                                acc.data_ptr()), "rd_soft_forward_batch")
+        if (w == w[0]).all() and (h == h[0]).all():
+            acc = acc.view(len(w), L, int(h[0]), int(w[0]))
+        return acc
+
+    def soft_backward_batch(self, xy, hess, offsets, sizes, params: dict, grad_acc: torch.Tensor) -> torch.Tensor:
+        """d/d(Ixx, Iyy, Ixy) per ridge of a batch from the accumulators' gradients (laid out as
+        soft_forward_batch returns them)."""
+        xy, hess = self._soft_inputs(xy, hess)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        w, h = self._sizes(sizes)
+        L = int(params["r_max"]) - int(params["r_min"]) + 3
+        g = grad_acc.to(device=self._dev(), dtype=torch.float32).contiguous()
+        if g.numel() != int((L * w.astype(np.int64) * h).sum()):
+            raise ValueError("grad_acc does not match the batch's accumulators")
+        out = torch.empty((xy.shape[0], 3), dtype=torch.float64, device=self._dev())
+        p = N.make_params(params)
+        N.check(self._lib.rd_soft_backward_batch(self._h, xy.data_ptr(), hess.data_ptr(), offs.ctypes.data,
+                                                 w.ctypes.data, h.ctypes.data, len(w), ctypes.byref(p),
+                                                 g.data_ptr(), out.data_ptr(), None), "rd_soft_backward_batch")
+        return out
+
+    def hessian_backward_batch(self, xy, grad_hess, offsets, sizes, params: dict,
+                               grad_img: torch.Tensor | None = None) -> torch.Tensor:
+        """Adds each frame's image gradient of its ridges' Hessian gradients into grad_img (the
+        frames' float32 planes back to back; zeros if None) and returns it."""
+        xy, grad_hess = self._soft_inputs(xy, grad_hess)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        w, h = self._sizes(sizes)
+        npx = int((w.astype(np.int64) * h).sum())
+        if grad_img is None:
+            grad_img = torch.zeros(npx, dtype=torch.float32, device=self._dev())
+        if grad_img.dtype != torch.float32 or not grad_img.is_contiguous() or grad_img.numel() != npx:
+            raise ValueError("grad_img must be a contiguous float32 tensor of the batch's pixels")
+        p = N.make_params(params)
+        N.check(self._lib.rd_hessian_backward_batch(self._h, xy.data_ptr(), grad_hess.data_ptr(), offs.ctypes.data,
+                                                    w.ctypes.data, h.ctypes.data, len(w), ctypes.byref(p),
+                                                    grad_img.data_ptr()), "rd_hessian_backward_batch")
+        return grad_img
+
+    def _frame_of(self, frame_of, m):
+        fo = torch.as_tensor(frame_of).to(device=self._dev(), dtype=torch.int32).contiguous().reshape(-1)
+        if fo.shape[0] != m:
+            raise ValueError("frame_of must have one entry per ring")
+        return fo
+
+    def fit_loss_batch(self, frames, theta, theta0, frame_of, s: float):
+        """Ring fit loss (float64 [m]) and (A, B) (float64 [m, 2]) of rings on up to 64 frames."""
+        arr = self._frame_array(frames)
+        theta, theta0 = self._thetas(theta), self._thetas(theta0)
+        m = theta.shape[0]
+        fo = self._frame_of(frame_of, m)
+        loss = torch.empty((m,), dtype=torch.float64, device=self._dev())
+        ab = torch.empty((m, 2), dtype=torch.float64, device=self._dev())
+        N.check(self._lib.rd_fit_loss_batch(self._h, arr, len(frames), fo.data_ptr(), theta.data_ptr(),
+                                            theta0.data_ptr(), m, float(s), loss.data_ptr(), ab.data_ptr()),
+                "rd_fit_loss_batch")
+        return loss, ab
+
+    def fit_loss_backward_batch(self, frames, theta, theta0, frame_of, s: float, grad_loss,
+                                grad_img: torch.Tensor | None = None):
+        """(grad_img with d/dI added to the frames' planes back to back, or None; d/dtheta
+        float64 [m, 3]) of sum_j grad_loss[j] L_j over up to 64 frames."""
+        arr = self._frame_array(frames)
+        theta, theta0 = self._thetas(theta), self._thetas(theta0)
+        m = theta.shape[0]
+        fo = self._frame_of(frame_of, m)
+        gl = torch.as_tensor(grad_loss).to(device=self._dev(), dtype=torch.float64).contiguous().reshape(-1)
+        if gl.shape[0] != m:
+            raise ValueError("grad_loss must have one entry per ring")
+        npx = sum(int(a.width) * int(a.height) for a in arr)
+        if grad_img is not None and (grad_img.dtype != torch.float32 or not grad_img.is_contiguous()
+                                     or grad_img.numel() != npx):
+            raise ValueError("grad_img must be a contiguous float32 tensor of the batch's pixels")
+        gt = torch.empty((m, 3), dtype=torch.float64, device=self._dev())
+        N.check(self._lib.rd_fit_loss_backward_batch(self._h, arr, len(frames), fo.data_ptr(), theta.data_ptr(),
+                                                     theta0.data_ptr(), m, float(s), gl.data_ptr(),
+                                                     grad_img.data_ptr() if grad_img is not None else None,
+                                                     gt.data_ptr()), "rd_fit_loss_backward_batch")
+        return grad_img, gt
+
     def _thetas(self, theta):
         return torch.as_tensor(theta).to(device=self._dev(), dtype=torch.float64).contiguous().reshape(-1, 3)
 

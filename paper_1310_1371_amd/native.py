@@ -93,6 +93,14 @@ SIGNATURES = {
     "rd_fit_loss": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp]),
     "rd_fit_loss_backward": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp, _vp]),
     "rd_profile_vote_phases": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp]),
+    "rd_soft_ridges_batch": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _P(RdParams), _vp, _vp, _i64, _vp]),
+    "rd_soft_forward_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _P(RdParams), _vp]),
+    "rd_soft_backward_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _P(RdParams), _vp, _vp,
+                                              _P(_i64)]),
+    "rd_hessian_backward_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _P(RdParams), _vp]),
+    "rd_fit_loss_batch": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _vp, _vp, _vp, _i64, ctypes.c_double, _vp, _vp]),
+    "rd_fit_loss_backward_batch": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _vp, _vp, _vp, _i64, ctypes.c_double,
+                                                  _vp, _vp, _vp]),
     "rd_refine": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _vp, _vp, _i64, ctypes.c_double, _i32, ctypes.c_double,
                                  _vp, _vp, _vp]),
     "rd_linker_create": (ctypes.c_int, [_P(RdLinkParams), _i32, _i32, _vp, _P(_vp)]),
