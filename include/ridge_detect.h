@@ -227,13 +227,15 @@ rd_status rd_measure_lds_atomics(int32_t device, int32_t with_return, double* at
 
 /* Measurement only: one rd_detect of `frame`, launched directly (no graph), with a
  * profiling instance of the vote kernel (steps 3-4) that reads the shader clock after the
- * barrier ending each phase of each tile.  clocks[0..5] (host) receive the clocks summed over
- * the workgroups of: tile set-up (queue, candidate bins, first histogram clear), ridge
- * staging and the item sort, votes with hotspot listing, scores, the above-threshold list,
- * and the 3x3x3 test with the next level chunk's clear; clocks[6] the workgroups' summed
- * lifetimes, clocks[7] the tiles, clocks[8] and clocks[9] the longest and the shortest
- * workgroup lifetime.  Same validation as rd_detect; RD_E_OVERFLOW as rd_detect. */
-#define RD_VOTE_PHASE_WORDS 10
+ * barrier ending each phase of each tile (and one barrier of its own between the 3x3x3 test
+ * and the next chunk's clear).  clocks[0..7] (host) receive the clocks summed over the
+ * workgroups of: tile set-up (queue, candidate bins, first histogram clear), ridge staging
+ * (records, level ranges), the item sort, votes with hotspot listing, scores, the
+ * above-threshold list, the 3x3x3 test with peak output, and the next level chunk's clear
+ * and weight rows; clocks[8] the workgroups' summed lifetimes, clocks[9] the tiles,
+ * clocks[10] and clocks[11] the longest and the shortest workgroup lifetime.  Same
+ * validation as rd_detect; RD_E_OVERFLOW as rd_detect. */
+#define RD_VOTE_PHASE_WORDS 12
 rd_status rd_profile_vote_phases(rd_handle h, const rd_frame* frame, const rd_params* params, uint64_t* clocks);
 
 /* ---- stage entry points (parity checks; same kernels as rd_detect) ------------------- */

@@ -106,7 +106,7 @@ struct VoteArgs {
 
 // Phases of the vote kernel's profiling instance (clocks summed over workgroups), then the
 // workgroups' summed lifetime, the tiles, the longest and the shortest lifetime
-enum { PH_SETUP = 0, PH_STAGE, PH_VOTE, PH_SCORE, PH_STRONG, PH_PEAK, PH_COUNT };
+enum { PH_SETUP = 0, PH_STAGE, PH_SORT, PH_VOTE, PH_SCORE, PH_STRONG, PH_PEAK, PH_PREP, PH_COUNT };
 
 // The tile-cost pass: every (ridge, sign) casts its vote at one level in COST_STEP into a
 // per-tile counter (the tile that holds the vote), an estimate of the tiles' vote work; a

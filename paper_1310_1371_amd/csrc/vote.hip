@@ -359,6 +359,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     }
                     for (int i = tid; i < 256; i += NT) sKey[i] = 0u;
                     __syncthreads();
+                    stamp(PH_STAGE);
                     // order the (ridge, sign) items whose range meets the tile by first level
                     // (counting sort): the lanes of a wave then run level loops of similar
                     // extent; the items that miss the tile (key 255, most of them) are dropped
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         if (key != 255u) sOrd[atomicAdd(&sKey[key], 1u)] = static_cast<uint16_t>(it);
                     }
                     __syncthreads();
-                    stamp(PH_STAGE);
+                    stamp(PH_SORT);
                 }
                 // votes: each staged (ridge, sign) item over its level range clipped to this
                 // chunk, split between two lanes (half of the levels each), which spreads the
@@ -763,9 +764,13 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 wlo = whi;
             }
             if (windows && !per_level) __syncthreads();       // the table in the histogram is done
+            if (PHASES) {                                     // the profiling instance splits here
+                __syncthreads();
+                stamp(PH_PEAK);
+            }
             if (c + 1 < a.nchunks) prepare(c + 1);
             __syncthreads();
-            stamp(PH_PEAK);
+            stamp(PH_PREP);
         }
     }
     if (PHASES && tid == 0) {

@@ -223,19 +223,20 @@ class Detector:
         return {name: (ms[i], n[i]) for i, name in enumerate(("ridge", "vote", "fit"))}
 
     # -------------------------------------------------------------------- stage outputs
-    PHASES = ("tile set-up", "staging and item sort", "votes and hotspot listing", "scores",
-              "above-threshold list", "3x3x3 test and next chunk clear")
+    PHASES = ("tile set-up", "ridge staging", "item sort", "votes and hotspot listing", "scores",
+              "above-threshold list", "3x3x3 test and peaks", "next chunk clear and weights")
 
     def profile_vote_phases(self, frame, params: dict) -> dict:
         """One detection with the phase-timed vote kernel: shader clocks per phase summed over
         the workgroups, their lifetimes, the tiles, the longest and shortest lifetime."""
         fr = _frame_struct(frame)
         p = N.make_params(params)
-        c = (ctypes.c_uint64 * 10)()
+        n = len(self.PHASES)
+        c = (ctypes.c_uint64 * (n + 4))()
         N.check(self._lib.rd_profile_vote_phases(self._h, ctypes.byref(fr), ctypes.byref(p), c),
                 "rd_profile_vote_phases")
-        return {"phases": dict(zip(self.PHASES, [int(v) for v in c[:6]])), "lifetime_sum": int(c[6]),
-                "tiles": int(c[7]), "lifetime_max": int(c[8]), "lifetime_min": int(c[9])}
+        return {"phases": dict(zip(self.PHASES, [int(v) for v in c[:n]])), "lifetime_sum": int(c[n]),
+                "tiles": int(c[n + 1]), "lifetime_max": int(c[n + 2]), "lifetime_min": int(c[n + 3])}
 
     def curvature(self, frame, params: dict):
         """k_- (float32 [H, W]) and direction codes (int16 [H, W, 2]) as CUDA tensors."""
