@@ -67,10 +67,10 @@ void build_fixed_tables(const rd_params& p, FixedTables& t, size_t budget) {
     while (c0 <= t.L - 2) {
         int c1 = c0 + 1;
         while (c1 <= t.L - 2 && c1 + 1 - c0 <= CHUNK_MAX &&
-               vote_lds_bytes(VOTE_TILE, c1 + 1 - c0 + 2, t.ktab[c1 + 1]) <= budget)
+               vote_lds_bytes(vote_tile_for(p.measure), c1 + 1 - c0 + 2, t.ktab[c1 + 1]) <= budget)
             ++c1;
         t.chunks[t.nchunks++] = c0;
-        t.lds = std::max(t.lds, vote_lds_bytes(VOTE_TILE, c1 - c0 + 2, t.ktab[c1]));
+        t.lds = std::max(t.lds, vote_lds_bytes(vote_tile_for(p.measure), c1 - c0 + 2, t.ktab[c1]));
         c0 = c1;
     }
     t.chunks[t.nchunks] = t.L - 1;
@@ -98,7 +98,7 @@ StencilArgs stencil_args_for(const rd_params& p, const FrameDesc* frames, int nf
 
 int gauss_radius(float sigma) { return static_cast<int>(std::ceil(4.0 * static_cast<double>(sigma))); }
 
-int vote_tiles(int W, int H) { return ((W + VOTE_TILE - 1) / VOTE_TILE) * ((H + VOTE_TILE - 1) / VOTE_TILE); }
+int vote_tiles(int W, int H, int T) { return ((W + T - 1) / T) * ((H + T - 1) / T); }
 
 int assign_chunks(rd_ctx* h, int n) {
     int tot = 0;
@@ -153,7 +153,7 @@ rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int var
         fd.peak0 = i * h->max_peaks;
         h->h_frames[i] = fd;
         tt += ((f.width + tw - 1) / tw) * ((f.height + th - 1) / th);
-        tv += vote_tiles(f.width, f.height);
+        tv += vote_tiles(f.width, f.height, h->vtile);
         bins += static_cast<int64_t>(fd.nbx) * fd.nby;
     }
     if (bins > h->max_bins) return RD_E_TOO_LARGE;
@@ -220,7 +220,8 @@ rd_status gather_ridges(rd_ctx* h, int32_t* xy, int16_t* q, float* k, int64_t ca
 namespace {
 
 rd_status upload_tables(rd_ctx* h, const rd_params& p) {
-    const size_t budget = static_cast<size_t>(h->tune.vote_lds_kb) * 1024;
+    h->vtile = vote_tile_for(p.measure);
+    const size_t budget = std::min<size_t>(static_cast<size_t>(h->tune.vote_lds_kb) * 1024, vote_lds_max(h->vtile));
     if (h->tab_valid && same_params(h->tab_params, p) && h->tab_budget == budget) return RD_OK;
     build_tables(p, h->tabs, budget);
     const LevelTables& t = h->tabs;
@@ -259,6 +260,7 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.error = h->d_counts + h->max_frames + 1;
     a.tile_counter = h->d_counts + h->max_frames + 2;
     a.stats = h->d_stats;
+    a.tile = vote_tile_for(p.measure);
     return a;
 }
 
@@ -330,6 +332,7 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
         ta.rstep = h->tabs.rstep;
         ta.nlevels = h->tabs.L;
         ta.total_vtiles = tv;
+        ta.tile = va.tile;
         ta.cost = h->d_tcost;
         ta.order = h->d_torder;
         RD_HIP(launch_tile_cost(ta, h->n_chunks, h->stream));
@@ -584,7 +587,7 @@ rd_status rd_level_tables(const rd_params* p, int32_t capacity_levels, int32_t* 
                           uint64_t* thr) {
     RD_TRY(rd_validate_params(p));
     LevelTables t;
-    build_tables(*p, t, VOTE_LDS_MAX);
+    build_tables(*p, t, vote_lds_max(vote_tile_for(p->measure)));
     if (capacity_levels < t.L) return RD_E_TRUNCATED;
     for (int i = 0; i < t.L; ++i) {
         if (ktab) ktab[i] = t.ktab[i];
@@ -895,7 +898,7 @@ rd_status rd_stage_accumulate(rd_handle h, const int32_t* xy_dev, const int16_t*
     const size_t vox = static_cast<size_t>(h->tabs.L) * width * height;
     if (score_dev) RD_HIP(hipMemsetAsync(score_dev, 0, vox * sizeof(uint64_t), h->stream));
     RD_HIP(launch_zero(h->d_counts, h->max_frames + 4, h->stream));
-    VoteArgs va = vote_args(h, *params, 1, vote_tiles(width, height));
+    VoteArgs va = vote_args(h, *params, 1, vote_tiles(width, height, h->vtile));
     va.acc_dump = acc_dev;
     va.score_dump = score_dev;
     va.stats = nullptr;
@@ -913,7 +916,7 @@ rd_status rd_detect_ridges(rd_handle h, const int32_t* xy_dev, const int16_t* q_
     *n_rings = 0;
     RD_TRY(ridge_setup(h, xy_dev, q_dev, n, width, height, params));
     h->mark_now = h->timing;                       // every call of this entry point is timed
-    const rd_status st = enqueue(h, *params, 1, RD_F32, 0, false, 0, vote_tiles(width, height), h->dh_rings,
+    const rd_status st = enqueue(h, *params, 1, RD_F32, 0, false, 0, vote_tiles(width, height, h->vtile), h->dh_rings,
                                  h->dh_counts);
     if (st != RD_OK) {
         h->mark_now = false;
@@ -964,6 +967,7 @@ rd_status rd_detect_encoded(rd_handle h, const uint8_t* enc, int32_t on_device, 
         if (capacities[i] < 0 || (capacities[i] > 0 && !out) || out_offsets[i] < 0) return RD_E_INVALID;
     }
     RD_HIP(hipSetDevice(h->device));
+    h->vtile = vote_tile_for(params->measure);      // the descriptors below count vote tiles of this size
     // the headers, checked on the host: magic, size, the stream long enough for its count
     std::vector<uint32_t> hdr(4 * static_cast<size_t>(n));
     for (int i = 0; i < n; ++i) {
@@ -997,7 +1001,7 @@ rd_status rd_detect_encoded(rd_handle h, const uint8_t* enc, int32_t on_device, 
         fd.bin0 = bins;
         fd.peak0 = i * h->max_peaks;
         h->h_frames[i] = fd;
-        tv += vote_tiles(W, H);
+        tv += vote_tiles(W, H, h->vtile);
         bins += nb;
         px += static_cast<int64_t>(W) * H;
     }

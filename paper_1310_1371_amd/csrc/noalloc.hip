@@ -95,7 +95,7 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
 
     // host-side tables and descriptor (stack only); the copies complete before the call returns
     FixedTables tabs;
-    build_fixed_tables(*params, tabs, VOTE_LDS_MAX);
+    build_fixed_tables(*params, tabs, vote_lds_max(vote_tile_for(params->measure)));
     const int W = frame->width, H = frame->height;
     const int rg = gauss_radius(params->sigma_smooth);
     int tw = 0, th = 0;
@@ -108,7 +108,7 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
     fd.nbx = (W + BIN - 1) / BIN;
     fd.nby = (H + BIN - 1) / BIN;
     const int tt = ((W + tw - 1) / tw) * ((H + th - 1) / th);
-    const int tv = vote_tiles(W, H);
+    const int tv = vote_tiles(W, H, vote_tile_for(params->measure));
 
     FrameDesc* d_frame = reinterpret_cast<FrameDesc*>(base + OFF_FRAME);
     uint32_t* d_wtab = reinterpret_cast<uint32_t*>(base + OFF_WTAB);
@@ -153,6 +153,7 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
     va.bin_count = d_bins;
     va.lbase = tabs.lbase;
     va.r_step = tabs.rstep;
+    va.tile = vote_tile_for(params->measure);
     va.nlevels = tabs.L;
     va.vote_threshold = params->vote_threshold;
     va.chunk_start = d_chunks;

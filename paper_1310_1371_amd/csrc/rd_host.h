@@ -108,6 +108,7 @@ struct rd_ctx {
     uint32_t* d_tcost = nullptr;
     unsigned long long* d_phase = nullptr;   // rd_profile_vote_phases: the clocks (allocated on first use)
     bool phase_on = false;
+    int vtile = rd::VOTE_TILE_RIDGE;        // vote tile of the parameters the tables were set up for
     uint32_t* d_torder = nullptr;
     int n_chunks = 0;                   // COST_CHUNK-bin chunks of the current launch's frames
     // pinned host memory; rings and counts are written by the fit kernel through mappings
@@ -147,7 +148,7 @@ namespace rd {
 
 // Shared host helpers (defined with the plain entry points).
 int gauss_radius(float sigma);
-int vote_tiles(int W, int H);
+int vote_tiles(int W, int H, int T);
 rd_status check_frame(const rd_ctx* h, const rd_frame* f);
 rd_status setup_frames(rd_ctx* h, const rd_frame* frames, int n, int rg, int variant, bool dense, int* total_tiles,
                        int* total_vtiles);

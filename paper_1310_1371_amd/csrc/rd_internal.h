@@ -102,6 +102,7 @@ struct VoteArgs {
     uint64_t* score_dump;
     const uint32_t* tile_order;  // [total_vtiles] the queue's tiles, estimated costliest first (may be null)
     unsigned long long* phase_clocks;  // profiling instance: [PH_COUNT + 4] (null: the plain kernel)
+    int32_t tile;                // T of the T x T vote tiles (VOTE_TILE_RIDGE or VOTE_TILE_EDGE)
 };
 
 // Phases of the vote kernel's profiling instance (clocks summed over workgroups), then the
@@ -124,6 +125,7 @@ struct TileCostArgs {
     const uint32_t* bin_count;
     int32_t rbase, rstep, nlevels;
     int32_t total_vtiles;        // <= ORDER_MAX
+    int32_t tile;                // T of the vote tiles
     uint32_t* cost;              // [ORDER_MAX]: the tiles' counters, zero before the counting kernel and
                                  // cleared again by the order kernel
     uint32_t* order;             // [total_vtiles]
@@ -204,8 +206,15 @@ constexpr int STENCIL_VARIANTS = 3;
 void stencil_tile_dims(int variant, int rg, bool dense, int* tw, int* th);
 hipError_t launch_stencil(const StencilArgs& a, int dtype, int rg, int variant, bool dense, hipStream_t s);
 
-constexpr int VOTE_TILE = 32;
-constexpr int VOTE_LDS_MAX = RD_VOTE_LDS_KB_MAX * 1024;   // dynamic LDS of the vote kernel (static ~70 KB)
+// Vote tiles of T x T pixels: 40 for directed ridges; 32 for directed edges, whose frames
+// list about twice the hotspots per area, so that a tile's list overflows into the
+// level-by-level fallback less often.  The tile size changes the work's split, no result.
+constexpr int VOTE_TILE_RIDGE = 40, VOTE_TILE_EDGE = 32;
+inline int vote_tile_for(int32_t measure) { return measure == RD_MEASURE_EDGE ? VOTE_TILE_EDGE : VOTE_TILE_RIDGE; }
+constexpr int VOTE_LDS_MAX = RD_VOTE_LDS_KB_MAX * 1024;   // dynamic LDS of the vote kernel, the largest instance
+// what each instance's static LDS (about 70 KB, and 6.5 KB more hotspot list for the larger
+// tile) leaves of a compute unit's 160 KiB; a tuning budget above it is clamped
+inline int vote_lds_max(int tile) { return tile == VOTE_TILE_EDGE ? VOTE_LDS_MAX : 83 * 1024; }
 constexpr int VOTE_NLEV_MAX = 20;          // accumulator levels per level chunk
 constexpr int VOTE_TABLE_BYTES = 8192;     // least dynamic LDS of a vote launch (the peak test's table)
 size_t vote_lds_bytes(int tile, int nlev_max, int kmax);

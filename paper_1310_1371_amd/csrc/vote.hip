@@ -70,17 +70,17 @@ constexpr int LMAX = R_LIMIT + 3;          // levels r_min - 1 .. r_max + 1 at m
 constexpr int NLEV_MAX = VOTE_NLEV_MAX;    // accumulator levels per level chunk
 constexpr int ACAP = 1536;                 // staged ridges (with a sign that can reach the tile)
 constexpr int PCAP = 160;                  // pieces of the candidate list (rounds of NT candidates)
-constexpr int HCAP = 1280;                 // hotspot list (>= (T + 2)^2 for the per-level fallback)
 constexpr int SCAP = 512;                  // above-threshold ("strong") voxels per chunk
 constexpr int WC = K_MAX + 8;              // centre tap of the padded weight row
 constexpr int NWW = WC + 4;                // u16 pairs per weight row: taps 0 .. 2 WC + 7
 constexpr int NS_HASH = 64;                // longer strong lists are tested through a hash table
 constexpr int HT = 2048;                   // its slots (u32), in the histogram's storage (free by then)
 static_assert(HT * 4 <= VOTE_TABLE_BYTES, "the launch gives the histogram at least the table's size");
-static_assert(HT * 4 <= HCAP * 12, "or the table lives in the hotspot list's storage");
-static_assert(SCAP <= 0xffff && (NLEV_MAX - 1) < 32, "table entries pack a 16-bit voxel key and a 16-bit index");
+constexpr int KEY_BITS = 11;               // score-region index bits of a table key
+static_assert(SCAP <= 0xffff && (NLEV_MAX - 1) < (1 << (16 - KEY_BITS)),
+              "table entries pack a 16-bit voxel key and a 16-bit index");
 
-// slot of a voxel key (level << 11 | index in the score region) in the strong-voxel table
+// slot of a voxel key (level << KEY_BITS | index in the score region) in the strong-voxel table
 __device__ __forceinline__ uint32_t strong_slot(uint32_t key) { return (key * 2654435761u) >> (32 - 11); }
 
 typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
@@ -96,7 +96,10 @@ __device__ __forceinline__ uint32_t dot2_u16(uint32_t a, uint32_t b, uint32_t c)
 template <int T, bool DUMP, bool PHASES = false>
 __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     constexpr int SR = T + 2, SR2 = SR * SR;
-    static_assert(SR2 <= HCAP, "per-level fallback needs a whole score region in the list");
+    // the hotspot list holds a whole score region (the per-level fallback lists one level's)
+    constexpr int HCAP = (SR2 + 255) / 256 * 256;
+    static_assert(HT * 4 <= HCAP * 12, "or the table lives in the hotspot list's storage");
+    static_assert(SR2 <= (1 << KEY_BITS), "a score-region index fits its part of the table key");
     constexpr int BINS_PER_SIDE = ((T + 2 + 2 * K_MAX + 2 * (R_LIMIT + 2)) >> BIN_SHIFT) + 2;
     static_assert(BINS_PER_SIDE * BINS_PER_SIDE <= NT, "one thread per candidate bin");
     extern __shared__ __align__(16) uint32_t sA[];           // u16 histogram, two per word
@@ -688,7 +691,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     __syncthreads();
                     for (int j = tid; j < ns; j += NT) {
                         const uint32_t e = sStrongId[j];
-                        const uint32_t key = ((e >> 16) << 11) | (e & 0xffffu);     // distinct per voxel
+                        const uint32_t key = ((e >> 16) << KEY_BITS) | (e & 0xffffu);     // distinct per voxel
                         // at most SCAP of HT slots are taken, so the probe ends
                         for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1))
                             if (atomicCAS(&sTab[slot], 0xffffffffu, (key << 16) | static_cast<uint32_t>(j)) == 0xffffffffu)
@@ -708,7 +711,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                             const int dy = o / 3 - 1, dx = o % 3 - 1;
                             if (dl == 0 && dy == 0 && dx == 0) continue;
                             // 1 <= sxr, syr <= T: the neighbour lies in the score region's index range
-                            const uint32_t key = (static_cast<uint32_t>(nl) << 11) |
+                            const uint32_t key = (static_cast<uint32_t>(nl) << KEY_BITS) |
                                                  static_cast<uint32_t>((syr + dy) * SR + sxr + dx);
                             for (uint32_t slot = strong_slot(key);; slot = (slot + 1) & (HT - 1)) {
                                 const uint32_t v = sTab[slot];
@@ -843,7 +846,7 @@ __global__ __launch_bounds__(CNT_) void k_tile_cost(TileCostArgs a) {
         if (tid < COST_CHUNK) sPre[tid + 1] = inc;
         if (tid == 0) sPre[0] = 0u;
     }
-    const int T = VOTE_TILE, W = fd.W, H = fd.H;
+    const int T = a.tile, W = fd.W, H = fd.H;
     const int tiles_x = (W + T - 1) / T;
     const int by0 = static_cast<int>(b0 / fd.nbx), by1 = static_cast<int>(blast / fd.nbx);
     const int bx0 = by0 == by1 ? static_cast<int>(b0 % fd.nbx) : 0;
@@ -991,27 +994,39 @@ size_t vote_lds_bytes(int tile, int nlev_max, int kmax) {
 }
 
 hipError_t vote_prepare() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, false, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vote<VOTE_TILE, true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, VOTE_LDS_MAX);
+    // every instance may take the whole opted-in dynamic LDS
+    const void* fns[] = {reinterpret_cast<const void*>(&k_vote<VOTE_TILE_RIDGE, false>),
+                         reinterpret_cast<const void*>(&k_vote<VOTE_TILE_RIDGE, false, true>),
+                         reinterpret_cast<const void*>(&k_vote<VOTE_TILE_RIDGE, true>),
+                         reinterpret_cast<const void*>(&k_vote<VOTE_TILE_EDGE, false>),
+                         reinterpret_cast<const void*>(&k_vote<VOTE_TILE_EDGE, false, true>),
+                         reinterpret_cast<const void*>(&k_vote<VOTE_TILE_EDGE, true>)};
+    for (int i = 0; i < 6; ++i) {
+        const int lds = vote_lds_max(i < 3 ? VOTE_TILE_RIDGE : VOTE_TILE_EDGE);
+        const hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int T>
+void launch_vote_t(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s) {
+    if (dump)
+        hipLaunchKernelGGL((k_vote<T, true>), dim3(blocks), dim3(NT), lds, s, a);
+    else if (a.phase_clocks)
+        hipLaunchKernelGGL((k_vote<T, false, true>), dim3(blocks), dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_vote<T, false>), dim3(blocks), dim3(NT), lds, s, a);
 }
 
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s) {
     if (a.total_vtiles <= 0 || a.nchunks <= 0) return hipSuccess;
-    if (lds > static_cast<size_t>(VOTE_LDS_MAX)) return hipErrorInvalidValue;   // beyond the opted-in size
+    if (lds > static_cast<size_t>(vote_lds_max(a.tile))) return hipErrorInvalidValue;   // beyond the opted-in size
     if (lds < static_cast<size_t>(VOTE_TABLE_BYTES)) lds = VOTE_TABLE_BYTES;
     if (blocks > a.total_vtiles) blocks = a.total_vtiles;   // persistent blocks take tiles from the queue
-    if (dump)
-        hipLaunchKernelGGL((k_vote<VOTE_TILE, true>), dim3(blocks), dim3(NT), lds, s, a);
-    else if (a.phase_clocks)
-        hipLaunchKernelGGL((k_vote<VOTE_TILE, false, true>), dim3(blocks), dim3(NT), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_vote<VOTE_TILE, false>), dim3(blocks), dim3(NT), lds, s, a);
+    if (a.tile == VOTE_TILE_RIDGE) launch_vote_t<VOTE_TILE_RIDGE>(a, lds, dump, blocks, s);
+    else if (a.tile == VOTE_TILE_EDGE) launch_vote_t<VOTE_TILE_EDGE>(a, lds, dump, blocks, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

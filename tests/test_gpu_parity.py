@@ -36,12 +36,21 @@ def _ragged():
 
 
 def _tail():
-    """161 x 97 float32, one column and one row past a multiple of the 32 px vote tile, with
-    rings centred on the last column and the last row: the last tiles' score regions are one
-    or two pixels wide."""
+    """161 x 97 float32, one column and one row past a multiple of 32 px (and a column past a
+    multiple of the 40 px vote tile), with rings centred on the last column and the last row:
+    the last tiles' score regions are one or two pixels wide."""
     cx, cy, R = np.array([160.0, 80.0]), np.array([48.0, 96.0]), np.array([20.0, 15.0])
     s, A = np.full(2, 1.5), np.ones(2)
     img = synth.render(161, 97, np.zeros((97, 161)), cx, cy, R, s, A)
+    return synth.Frame(img.astype(np.float32), cx, cy, R, s, A, dict(synth.PARAMS_C1), 0)
+
+
+def _tail40():
+    """121 x 81 float32, one column and one row past a multiple of the 40 px vote tile, with
+    rings centred on the last column and the last row."""
+    cx, cy, R = np.array([120.0, 60.0]), np.array([30.0, 80.0]), np.array([18.0, 14.0])
+    s, A = np.full(2, 1.5), np.ones(2)
+    img = synth.render(121, 81, np.zeros((81, 121)), cx, cy, R, s, A)
     return synth.Frame(img.astype(np.float32), cx, cy, R, s, A, dict(synth.PARAMS_C1), 0)
 
 
@@ -69,6 +78,7 @@ CASES = {
     "ragged_300x170_u16": _ragged,
     "min_32x32_f32": lambda: synth.single_ring(32, 32, 15.0, 16.0, 9.3),
     "tail_161x97_f32": _tail,
+    "tail_121x81_f32": _tail40,
     "big_ring_300_f32": _big_ring,
     "concentric_300_f32": _concentric,
 }
@@ -167,7 +177,7 @@ def _oracle_ridge_inputs(f):
     return xs, ys, qx, qy, xy, q
 
 
-@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32",
+@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32", "tail_121x81_f32",
                                   "big_ring_300_f32", "concentric_300_f32"])
 def test_accumulator_and_scores_bit_exact(det, name):
     say(f"[accumulate] {name}")
@@ -298,7 +308,7 @@ def _match(ref, got):
     return kr, kg
 
 
-@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32",
+@pytest.mark.parametrize("name", ["c1_256_f32", "ragged_300x170_u16", "min_32x32_f32", "tail_161x97_f32", "tail_121x81_f32",
                                   "big_ring_300_f32", "concentric_300_f32"])
 def test_rings_from_oracle_ridges_exact(det, name):
     say(f"[rings from oracle ridges] {name}")
