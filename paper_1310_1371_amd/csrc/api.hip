@@ -17,7 +17,6 @@ namespace {
 
 constexpr double TWO_PI = 6.283185307179586;
 constexpr double S_SCALE = 1073741824.0;   // 2^30
-constexpr int CHUNK_MAX = VOTE_NLEV_MAX - 2;   // peak levels per level chunk
 constexpr int NSTATS = 8 + 64;             // u64: votes, hotspots, strong, taps, -, -, -, -, 64 ridge stripes
 
 double level_sigma(const rd_params& p, int r) {
@@ -35,7 +34,6 @@ void build_tables(const rd_params& p, LevelTables& t, size_t budget) {
     t.wtab.assign(f.wtab, f.wtab + static_cast<size_t>(f.L) * (K_MAX + 1));
     t.ktab.assign(f.ktab, f.ktab + f.L);
     t.thr.assign(f.thr, f.thr + f.L);
-    t.chunks.assign(f.chunks, f.chunks + f.nchunks + 1);
     t.lds = f.lds;
 }
 
@@ -59,21 +57,10 @@ void build_fixed_tables(const rd_params& p, FixedTables& t, size_t budget) {
         t.thr[i] = static_cast<uint64_t>(
             std::floor(static_cast<double>(p.peak_fraction) * TWO_PI * static_cast<double>(l) * S_SCALE));
     }
-    // greedy level chunks over the peak level indices 1 .. L - 2: peak levels [c0, c1) need
-    // accumulator levels c0 - 1 .. c1
-    t.nchunks = 0;
-    t.lds = 0;
-    int c0 = 1;
-    while (c0 <= t.L - 2) {
-        int c1 = c0 + 1;
-        while (c1 <= t.L - 2 && c1 + 1 - c0 <= CHUNK_MAX &&
-               vote_lds_bytes(vote_tile_for(p.measure), c1 + 1 - c0 + 2, t.ktab[c1 + 1]) <= budget)
-            ++c1;
-        t.chunks[t.nchunks++] = c0;
-        t.lds = std::max(t.lds, vote_lds_bytes(vote_tile_for(p.measure), c1 - c0 + 2, t.ktab[c1]));
-        c0 = c1;
-    }
-    t.chunks[t.nchunks] = t.L - 1;
+    // the vote kernel's histogram storage: the budget, or the largest chunk of one peak level
+    // (three planes at the top level's window, K growing with the level) if that is larger.
+    // The kernel cuts each tile's level chunks to fit.
+    t.lds = std::max(budget, vote_lds_bytes(vote_tile_for(p.measure), 3, t.ktab[t.L - 1]));
 }
 
 StencilArgs stencil_args_for(const rd_params& p, const FrameDesc* frames, int nframes, int total_tiles) {
@@ -228,8 +215,6 @@ rd_status upload_tables(rd_ctx* h, const rd_params& p) {
     RD_HIP(hipMemcpyAsync(h->d_wtab, t.wtab.data(), t.wtab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
     RD_HIP(hipMemcpyAsync(h->d_ktab, t.ktab.data(), t.ktab.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
     RD_HIP(hipMemcpyAsync(h->d_thr, t.thr.data(), t.thr.size() * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
-    RD_HIP(hipMemcpyAsync(h->d_chunks, t.chunks.data(), t.chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                          h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));   // the host vectors may change on the next call
     h->tab_params = p;
     h->tab_budget = budget;
@@ -242,7 +227,6 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.frames = h->d_frames;
     a.nframes = nframes;
     a.total_vtiles = total_vtiles;
-    a.nchunks = static_cast<int32_t>(h->tabs.chunks.size()) - 1;
     a.rxy = h->d_rxy;
     a.rq = h->d_rq;
     a.bin_count = h->d_bin_count;
@@ -250,7 +234,6 @@ VoteArgs vote_args(rd_ctx* h, const rd_params& p, int nframes, int total_vtiles)
     a.r_step = h->tabs.rstep;
     a.nlevels = h->tabs.L;
     a.vote_threshold = p.vote_threshold;
-    a.chunk_start = h->d_chunks;
     a.wtab = h->d_wtab;
     a.ktab = h->d_ktab;
     a.thr = h->d_thr;
@@ -363,7 +346,6 @@ rd_status run_pipeline(rd_ctx* h, const rd_params& p, int nframes, int dtype, in
         k.variant = h->tune.stencil_tile;
         k.total_tiles = tt;
         k.total_vtiles = tv;
-        k.nchunks = static_cast<int>(h->tabs.chunks.size()) - 1;
         k.blocks = h->cus;
         k.lds = h->tabs.lds;
         k.bin_chunks = h->n_chunks;
@@ -645,7 +627,6 @@ rd_status rd_create(const rd_create_info* info, rd_handle* out) {
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_wtab), (R_LIMIT + 3) * (K_MAX + 1) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_ktab), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_thr), (R_LIMIT + 3) * sizeof(uint64_t)) == hipSuccess;
-    ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_chunks), (R_LIMIT + 3) * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_offsets), bins_single * sizeof(int64_t)) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&h->d_pixmask), bins_single * 8 * sizeof(uint32_t)) == hipSuccess;
     h->max_chunks = h->max_bins / RIDGE_CHUNK + h->max_frames + 1;
@@ -692,7 +673,6 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_wtab);
     (void)hipFree(h->d_ktab);
     (void)hipFree(h->d_thr);
-    (void)hipFree(h->d_chunks);
     (void)hipFree(h->d_offsets);
     (void)hipFree(h->d_pixmask);
     (void)hipFree(h->d_cbase);

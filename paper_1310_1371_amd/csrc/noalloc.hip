@@ -29,8 +29,7 @@ constexpr int64_t OFF_FRAME = OFF_COUNTS_OUT + 256;
 constexpr int64_t OFF_WTAB = OFF_FRAME + align256(sizeof(FrameDesc));
 constexpr int64_t OFF_KTAB = OFF_WTAB + align256((R_LIMIT + 3) * (K_MAX + 1) * 4);
 constexpr int64_t OFF_THR = OFF_KTAB + align256((R_LIMIT + 3) * 4);
-constexpr int64_t OFF_CHUNKS = OFF_THR + align256((R_LIMIT + 3) * 8);
-constexpr int64_t NA_TOTAL = OFF_CHUNKS + align256((R_LIMIT + 4) * 4);
+constexpr int64_t NA_TOTAL = OFF_THR + align256((R_LIMIT + 3) * 8);
 static_assert(NA_TOTAL <= RD_NOALLOC_SCRATCH_BYTES, "the layout must fit the declared size");
 
 // d_counts words as the kernels of a one-frame launch use them: [0] peaks of the frame,
@@ -114,7 +113,6 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
     uint32_t* d_wtab = reinterpret_cast<uint32_t*>(base + OFF_WTAB);
     int32_t* d_ktab = reinterpret_cast<int32_t*>(base + OFF_KTAB);
     uint64_t* d_thr = reinterpret_cast<uint64_t*>(base + OFF_THR);
-    int32_t* d_chunks = reinterpret_cast<int32_t*>(base + OFF_CHUNKS);
     uint32_t* d_rxy = reinterpret_cast<uint32_t*>(base + OFF_RXY);
     uint32_t* d_rq = reinterpret_cast<uint32_t*>(base + OFF_RQ);
     float* d_rk = reinterpret_cast<float*>(base + OFF_RK);
@@ -129,7 +127,6 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
                           hipMemcpyHostToDevice, s));
     RD_HIP(hipMemcpyAsync(d_ktab, tabs.ktab, tabs.L * sizeof(int32_t), hipMemcpyHostToDevice, s));
     RD_HIP(hipMemcpyAsync(d_thr, tabs.thr, tabs.L * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    RD_HIP(hipMemcpyAsync(d_chunks, tabs.chunks, (tabs.nchunks + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
     // what the kernels read before writing: the peak count, the error flag and the tile
     // queue (the bin counts are written for every bin of the frame by the ridge kernel)
@@ -147,7 +144,6 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
     va.frames = d_frame;
     va.nframes = 1;
     va.total_vtiles = tv;
-    va.nchunks = tabs.nchunks;
     va.rxy = d_rxy;
     va.rq = d_rq;
     va.bin_count = d_bins;
@@ -156,7 +152,6 @@ extern "C" rd_status rd_detect_noalloc(const rd_frame* frame, const rd_params* p
     va.tile = vote_tile_for(params->measure);
     va.nlevels = tabs.L;
     va.vote_threshold = params->vote_threshold;
-    va.chunk_start = d_chunks;
     va.wtab = d_wtab;
     va.ktab = d_ktab;
     va.thr = d_thr;

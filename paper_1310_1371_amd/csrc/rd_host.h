@@ -28,17 +28,15 @@ struct LevelTables {
     std::vector<uint32_t> wtab;      // L x (K_MAX + 1)
     std::vector<int32_t> ktab;       // L
     std::vector<uint64_t> thr;       // L
-    std::vector<int32_t> chunks;     // chunk boundaries over r_min .. r_max + 1
-    size_t lds = 0;
+    size_t lds = 0;                  // vote-histogram storage (dynamic LDS) of the launch
 };
 
 // The same tables in fixed-size arrays (no heap), for the entry point that allocates nothing.
 struct FixedTables {
-    int lbase = 0, rstep = 1, L = 0, nchunks = 0;
+    int lbase = 0, rstep = 1, L = 0;
     uint32_t wtab[(R_LIMIT + 3) * (K_MAX + 1)];
     int32_t ktab[R_LIMIT + 3];
     uint64_t thr[R_LIMIT + 3];
-    int32_t chunks[R_LIMIT + 4];
     size_t lds = 0;
 };
 
@@ -56,14 +54,14 @@ inline bool same_params(const rd_params& a, const rd_params& b) {
 // Everything a captured launch sequence bakes into its kernel arguments and grids; frame
 // pointers and sizes live in the device-side descriptor table and may change freely.
 struct GraphKey {
-    int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, nchunks = 0, blocks = 0;
+    int nframes = 0, dtype = 0, rg = 0, variant = 0, total_tiles = 0, total_vtiles = 0, blocks = 0;
     int bin_chunks = 0;
     bool timing = false;   // the graph holds the timing events' record nodes
     size_t lds = 0;
     rd_params params{};
     bool operator==(const GraphKey& o) const {
         return nframes == o.nframes && dtype == o.dtype && rg == o.rg && variant == o.variant && timing == o.timing &&
-               total_tiles == o.total_tiles && total_vtiles == o.total_vtiles && nchunks == o.nchunks &&
+               total_tiles == o.total_tiles && total_vtiles == o.total_vtiles &&
                blocks == o.blocks && lds == o.lds && bin_chunks == o.bin_chunks && same_params(params, o.params);
     }
 };
@@ -94,7 +92,6 @@ struct rd_ctx {
     uint32_t* d_wtab = nullptr;
     int32_t* d_ktab = nullptr;
     uint64_t* d_thr = nullptr;
-    int32_t* d_chunks = nullptr;
     int64_t* d_offsets = nullptr;       // stage gather offsets (per bin of one frame)
     uint32_t* d_pixmask = nullptr;      // caller ridge lists: one bit per pixel of one frame's bins
     // encoded ridge streams: per-chunk record bases (256 bins a chunk), per-frame ridge counts,

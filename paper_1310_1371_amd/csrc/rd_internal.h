@@ -80,7 +80,7 @@ struct VoteArgs {
     const FrameDesc* frames;
     int32_t nframes;
     int32_t total_vtiles;
-    int32_t nchunks;
+    int32_t hist_bytes;       // dynamic LDS of the launch: histogram planes of a level chunk (set by launch_vote)
     const uint32_t* rxy;
     const uint32_t* rq;
     const uint32_t* bin_count;
@@ -88,7 +88,6 @@ struct VoteArgs {
     int32_t r_step;           // level i has radius lbase + r_step i
     int32_t nlevels;          // L = (r_max - r_min) / r_step + 3
     int32_t vote_threshold;
-    const int32_t* chunk_start;  // [nchunks + 1] peak-level boundaries (level indices)
     const uint32_t* wtab;        // [level][K_MAX + 1] 15-bit weight factors
     const int32_t* ktab;         // [level] window half-width
     const uint64_t* thr;         // [level] integer score threshold

@@ -6,7 +6,10 @@
 // widest accumulator region, with each sign's level range clipped to that region, and orders
 // the (ridge, sign) items that can reach the tile by first level.  It then walks the level
 // chunks; a chunk of peak levels [rc0, rc1) needs the raw accumulator of levels rc0 - 1 .. rc1
-// on the tile grown by 1 px (the 3x3x3 box) plus the smoothing half-width K, so per chunk it:
+// on the tile grown by 1 px (the 3x3x3 box) plus the smoothing half-width K.  The chunks are
+// cut per tile to fill the LDS histogram, and a chunk's two top levels are the next chunk's
+// two bottom ones: their strong voxels (step 4) pass to the next chunk, which then holds and
+// votes only its new levels.  Per chunk it:
 //   1. clears a u16 histogram of those levels in LDS (two counters per 32-bit word);
 //   2. adds every item's votes over its level range with LDS atomics (exact integers: the
 //      direction is the fixed-point code, offset floor((r q + 2^13) / 2^14));
@@ -120,8 +123,14 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ unsigned long long sStrongS[SCAP];
     __shared__ uint32_t sStrongId[SCAP];
     __shared__ uint8_t sBad[SCAP];                           // strong voxel beaten by a neighbour
-    __shared__ uint32_t sBinPre[NT + 1];
+    __shared__ __align__(8) uint32_t sBinPre[NT + 1];
     __shared__ uint32_t sBinId[NT];
+    // strong voxels handed from a chunk to the next (its two top levels are the next chunk's
+    // two bottom levels): in the candidate-bin tables, which a tile staged in one piece does
+    // not read after its first chunk's staging
+    static_assert(SCAP * 8 <= (NT + 1) * 4 && SCAP <= NT, "the carried list fits the bin tables");
+    unsigned long long* const sCarryS = reinterpret_cast<unsigned long long*>(sBinPre);
+    uint32_t* const sCarryId = sBinId;
     __shared__ uint16_t sWt[LMAX][K_MAX + 1];                // 15-bit weight factors
     // per chunk level: weights W(|o - WC|) of taps o = 0 .. 2 WC + 8 (zero beyond K), as u16
     // pairs starting at even (sWpE) and odd (sWpO) taps, for two-tap dot products
@@ -130,9 +139,8 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     __shared__ int sTile, sFrame;
     __shared__ unsigned long long sThr[LMAX];
     __shared__ int32_t sKt[LMAX];
-    __shared__ int32_t sChunk[LMAX + 1];
     __shared__ uint32_t sWave[NW];
-    __shared__ uint32_t sNh, sNs;
+    __shared__ uint32_t sNh, sNs, sGat;
     __shared__ uint32_t sLevN[NLEV_MAX];                      // strong voxels per chunk level
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -157,7 +165,6 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         sThr[i] = a.thr[i];
         sKt[i] = a.ktab[i];
     }
-    for (int i = tid; i <= a.nchunks; i += NT) sChunk[i] = a.chunk_start[i];
     if (a.nframes <= FRAMES_LDS)
         for (int i = tid; i < a.nframes; i += NT) sVt0[i] = a.frames[i].vtile0;
     __syncthreads();
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     const int rbase = a.lbase, rstep = a.r_step;
     auto radius = [&](int i) { return rbase + rstep * i; };
     const float inv_step = 1.0f / static_cast<float>(rstep);   // exact for rstep = 1
-    const int i_hi = sChunk[a.nchunks];                        // the top level, L - 1
+    const int i_hi = L - 1;                                    // the top level
     const uint32_t tint = static_cast<uint32_t>(a.vote_threshold);
     uint32_t st_votes = 0;                                              // statistics
     unsigned long long st_hot = 0, st_strong = 0, st_taps = 0;
@@ -233,18 +240,40 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         }
         const int nrounds = static_cast<int>((total + NT - 1) / NT);
 
-        // clear chunk c's histogram, fill its weight rows and empty its hotspot list; chunk 0
-        // here, chunk c + 1 during chunk c's 3x3x3 phase, which touches none of these
-        auto prepare = [&](int c) {
-            const int l0 = sChunk[c] - 1, l1 = sChunk[c + 1];
+        // Level chunks are cut per tile: a chunk of peak levels [c0, c1) needs the accumulator
+        // planes of levels c0 - 1 .. c1 on the tile grown by 1 + K(c1) px (clipped to the
+        // frame), except the two bottom ones when the previous chunk handed over their strong
+        // voxels (skip = 2).  The chunk takes the most peak levels whose planes fit the
+        // launch's histogram storage, at least one (which always fits: the launch holds any
+        // one-level chunk of an unclipped tile, and K grows with the level).
+        auto plane_u16 = [&](int K) {
+            const int AW = min(sx1 + K, W) - max(sx0 - K, 0), AH = min(sy1 + K, H) - max(sy0 - K, 0);
+            return ((AW + 8) & ~7) * AH;
+        };
+        auto chunk_end = [&](int c0, int skip) {
+            // lane i tests the end c0 + 2 + i (accumulator levels c0 - 1 .. c0 + 2 + i); the
+            // sizes grow with i, so the chunk ends before the first lane that fails
+            const int e = c0 + 2 + lane, nl = e - c0 + 2;
+            const bool fits = e <= L - 1 && nl <= NLEV_MAX && 2 * (nl - skip) * plane_u16(sKt[e]) <= a.hist_bytes;
+            return c0 + 1 + __builtin_ctzll(~__ballot(fits));   // lane NLEV_MAX - 3 fails
+        };
+        // clear a chunk's histogram, fill its weight rows and empty its hotspot list; the first
+        // chunk's here, the next one's during a chunk's 3x3x3 phase, which touches none of these.
+        // A chunk that takes over ncar >= 0 strong voxels of its two bottom levels has no planes
+        // for them (plane i of the storage holds local level i + skip) and opens its hotspot list
+        // with the carried voxels and their scores.
+        auto prepare = [&](int c0, int c1, int ncar) {
+            const int l0 = c0 - 1, l1 = c1;
             const int nlev = l1 - l0 + 1;
-            const int Kc = sKt[l1];
-            const int AW = min(sx1 + Kc, W) - max(sx0 - Kc, 0), AH = min(sy1 + Kc, H) - max(sy0 - Kc, 0);
-            const int words = (nlev * ((AW + 8) & ~7) * AH) >> 1;
+            const int words = ((nlev - (ncar >= 0 ? 2 : 0)) * plane_u16(sKt[l1])) >> 1;   // whole uint4s
             uint4* a4 = reinterpret_cast<uint4*>(sA);
             const uint4 z = make_uint4(0u, 0u, 0u, 0u);
             for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
             for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
+            for (int i = tid; i < ncar; i += NT) {
+                sHot[i] = sCarryId[i];
+                sHS[i] = sCarryS[i];
+            }
             for (int i = tid; i < nlev * NWW; i += NT) {
                 const int li = i / NWW, j = i - li * NWW;
                 const int lg = l0 + li, K = sKt[lg];
@@ -257,15 +286,21 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 sWpE[li][j] = wl[0] | (wl[1] << 16);
                 sWpO[li][j] = wl[1] | (wl[2] << 16);
             }
-            if (tid == 0) sNh = 0;
+            if (tid == 0) sNh = ncar > 0 ? static_cast<uint32_t>(ncar) : 0u;
         };
-        prepare(0);
+        int carry_n = -1;                                     // voxels carried into the next chunk
+        int rc0 = 1, rc1 = chunk_end(1, 0);                   // the chunk's peak levels [rc0, rc1)
+        prepare(rc0, rc1, -1);
         __syncthreads();
         stamp(PH_SETUP);
         if (PHASES) ++ph_tiles;
 
-        for (int c = 0; c < a.nchunks; ++c) {
-            const int rc0 = sChunk[c], rc1 = sChunk[c + 1];
+        for (bool first_chunk = true;; first_chunk = false) {
+            // local levels below `skip` were scored by the previous chunk, which handed over
+            // their ncar strong voxels (the scores of a level do not depend on the chunk: its
+            // window lies inside every chunk's accumulator region that holds the level)
+            const int skip = carry_n >= 0 ? 2 : 0, ncar = max(carry_n, 0);
+            carry_n = -1;
             const int l0 = rc0 - 1, l1 = rc1;                // accumulator level indices, inclusive
             const int nlev = l1 - l0 + 1;
             const int Kc = sKt[l1];                           // widest window of the chunk
@@ -276,15 +311,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             const int plane = AWP * AH;                       // u16 per level, multiple of 8
             // the score region (tile + 1 px) in histogram coordinates
             const int hu0 = sx0 - ax0, hw = sx1 - sx0, hv0 = sy0 - ay0, hh = sy1 - sy0;
-            if (tid == 0) sNs = 0;                            // last read by the previous 3x3x3 phase
+            if (tid == 0) {                                   // last read by the previous 3x3x3 phase
+                sNs = 0;
+                sGat = 0;                                     // and before the previous prepare
+            }
             if (tid < NLEV_MAX) sLevN[tid] = 0u;
             // ---- votes of the staged ridges.  Only ridges with a sign that can reach the tile
             // are staged.  They are staged once per tile when they fit (ACAP); otherwise the
             // first chunk cuts the candidate list into pieces of whole rounds of NT candidates
             // that fit, and every chunk restages the pieces one after another.
             for (int pc = 0;; ++pc) {
-                if (c == 0 || sNPieces > 1) {
-                    const int rend = c == 0 ? nrounds : sCur[pc + 1];
+                if (first_chunk || sNPieces > 1) {
+                    const int rend = first_chunk ? nrounds : sCur[pc + 1];
                     uint32_t pn = 0;
                     int rd = sCur[pc];
                     for (; rd < rend; ++rd) {
@@ -351,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         pn += tot;
                         __syncthreads();                          // sWave is rewritten next round
                     }
-                    if (c == 0 && tid == 0) {
+                    if (first_chunk && tid == 0) {
                         sCur[pc + 1] = rd;
                         if (rd >= nrounds) {
                             sNPieces = pc + 1;
@@ -407,7 +445,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const uint32_t rr = sRidR[jr] >> (16 * sg);
                     const int la_raw = static_cast<int>(rr & 0xffu);
                     if (la_raw > l1) break;                       // the rest start later still
-                    const int la0 = max(la_raw, l0), lb0 = min(static_cast<int>((rr >> 8) & 0xffu), l1);
+                    const int la0 = max(la_raw, l0 + skip), lb0 = min(static_cast<int>((rr >> 8) & 0xffu), l1);
                     const int mid = (la0 + lb0) >> 1;
                     const int la = (k & 1) ? mid + 1 : la0, lb = (k & 1) ? lb0 : mid;
                     if (la > lb) continue;
@@ -424,7 +462,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int stx = rstep * sqx, sty = rstep * sqy;
                     // byte offsets of the u16 counters: 2 u within a row, row stride 2 AWP
                     const int x2 = 2 * x, AW2 = 2 * AW, AWP2 = 2 * AWP;
-                    int base = 2 * (la - l0) * plane;
+                    int base = 2 * (la - l0 - skip) * plane;
                     // the vote that lifts a counter past T_int lists the voxel as a hotspot, once,
                     // if it lies in the score region (the tile grown by 1 px).  The slot is taken
                     // at one level step and written at the next, so the wait for the slot comes
@@ -546,13 +584,24 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     if (tid == 0) sNh = 0;
                     __syncthreads();
                     const int SW = sx1 - sx0;
-                    for (int i = tid; i < SW * SHh; i += NT) {
-                        const int vy = sy0 + i / SW, vx = sx0 + i % SW;
-                        if (get_u16(sA, pass * plane + (vy - ay0) * AWP + (vx - ax0)) > tint) {
-                            const uint32_t h = atomicAdd(&sNh, 1u);
-                            sHot[h] = (static_cast<uint32_t>(pass) << 16) |
-                                      static_cast<uint32_t>((vy - (y0 - 1)) * SR + (vx - (x0 - 1)));
-                            sHS[h] = 0ull;
+                    if (pass < skip) {                        // a carried level: its strong voxels
+                        for (int i = tid; i < ncar; i += NT) {
+                            const uint32_t e = sCarryId[i];
+                            if (static_cast<int>(e >> 16) == pass) {
+                                const uint32_t h = atomicAdd(&sNh, 1u);
+                                sHot[h] = e;
+                                sHS[h] = sCarryS[i];
+                            }
+                        }
+                    } else {
+                        for (int i = tid; i < SW * SHh; i += NT) {
+                            const int vy = sy0 + i / SW, vx = sx0 + i % SW;
+                            if (get_u16(sA, (pass - skip) * plane + (vy - ay0) * AWP + (vx - ax0)) > tint) {
+                                const uint32_t h = atomicAdd(&sNh, 1u);
+                                sHot[h] = (static_cast<uint32_t>(pass) << 16) |
+                                          static_cast<uint32_t>((vy - (y0 - 1)) * SR + (vx - (x0 - 1)));
+                                sHS[h] = 0ull;
+                            }
                         }
                     }
                     __syncthreads();
@@ -568,6 +617,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int sub = task - h * ntk, bi = sub >> 1, half = sub & 1;
                     const uint32_t e = sHot[h];
                     const int li = e >> 16, sidx = e & 0xffff;
+                    if (li < skip) continue;                       // carried with its score
                     const int lg = l0 + li;
                     const int K = sKt[lg];
                     const int vx = x0 - 1 + sidx % SR, vy = y0 - 1 + sidx / SR;
@@ -588,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int dlo = half ? (K >> 1) + 1 : 0, dhi = half ? K : (K >> 1);
                     const int up_max = vy - ay0, dn_max = ay1 - 1 - vy;   // farthest rows in the region
                     const int rstep = AWP >> 3;
-                    const uint4* rowc = reinterpret_cast<const uint4*>(sA) + ((li * plane + (vy - ay0) * AWP + c0) >> 3);
+                    const uint4* rowc = reinterpret_cast<const uint4*>(sA) + (((li - skip) * plane + (vy - ay0) * AWP + c0) >> 3);
                     const uint16_t* wv = &sWt[lg][0];
                     unsigned long long acc = 0;
                     auto band = [&](const uint4 q) {
@@ -644,10 +694,23 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 if (first) {
                     const uint32_t ns_all = sNs;
                     if (tid == 0) {
-                        st_hot += nh_all;
-                        st_strong += static_cast<unsigned long long>(ns_all);
+                        st_hot += nh_all - ncar;
+                        st_strong += static_cast<unsigned long long>(ns_all - ncar);
                     }
                     windows = ns_all > static_cast<uint32_t>(SCAP);
+                    // the next chunk's two bottom levels are this chunk's two top levels: hand
+                    // their strong voxels over (all of them are in the list unless it overflowed)
+                    if (!DUMP && !windows && rc1 <= L - 2 && sNPieces == 1) {
+                        for (int j = tid; j < static_cast<int>(ns_all); j += NT) {
+                            const uint32_t e = sStrongId[j];
+                            if (static_cast<int>(e >> 16) >= nlev - 2) {
+                                const uint32_t k = atomicAdd(&sGat, 1u);       // < SCAP
+                                sCarryId[k] = e - (static_cast<uint32_t>(nlev - 2) << 16);
+                                sCarryS[k] = sStrongS[j];
+                            }
+                        }
+                        carry_n = 0;                           // counted after the next barrier
+                    }
                     if (windows) continue;                     // round 1 takes the first window
                 }
                 const bool in_hist = windows && !per_level;
@@ -771,9 +834,19 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 __syncthreads();
                 stamp(PH_PEAK);
             }
-            if (c + 1 < a.nchunks) prepare(c + 1);
+            if (carry_n >= 0) {
+                __syncthreads();                              // the carried list is complete
+                carry_n = static_cast<int>(sGat);
+            }
+            const bool last = rc1 > L - 2;
+            if (!last) {
+                rc0 = rc1;
+                rc1 = chunk_end(rc0, carry_n >= 0 ? 2 : 0);
+                prepare(rc0, rc1, carry_n);
+            }
             __syncthreads();
             stamp(PH_PREP);
+            if (last) break;
         }
     }
     if (PHASES && tid == 0) {
@@ -1020,12 +1093,14 @@ void launch_vote_t(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStre
 }
 
 hipError_t launch_vote(const VoteArgs& a, size_t lds, bool dump, int blocks, hipStream_t s) {
-    if (a.total_vtiles <= 0 || a.nchunks <= 0) return hipSuccess;
+    if (a.total_vtiles <= 0 || a.nlevels < 3) return hipSuccess;
     if (lds > static_cast<size_t>(vote_lds_max(a.tile))) return hipErrorInvalidValue;   // beyond the opted-in size
     if (lds < static_cast<size_t>(VOTE_TABLE_BYTES)) lds = VOTE_TABLE_BYTES;
     if (blocks > a.total_vtiles) blocks = a.total_vtiles;   // persistent blocks take tiles from the queue
-    if (a.tile == VOTE_TILE_RIDGE) launch_vote_t<VOTE_TILE_RIDGE>(a, lds, dump, blocks, s);
-    else if (a.tile == VOTE_TILE_EDGE) launch_vote_t<VOTE_TILE_EDGE>(a, lds, dump, blocks, s);
+    VoteArgs b = a;
+    b.hist_bytes = static_cast<int32_t>(lds);                 // the kernel cuts its level chunks to fit
+    if (a.tile == VOTE_TILE_RIDGE) launch_vote_t<VOTE_TILE_RIDGE>(b, lds, dump, blocks, s);
+    else if (a.tile == VOTE_TILE_EDGE) launch_vote_t<VOTE_TILE_EDGE>(b, lds, dump, blocks, s);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
