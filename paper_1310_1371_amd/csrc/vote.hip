@@ -259,21 +259,16 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         };
         // clear a chunk's histogram, fill its weight rows and empty its hotspot list; the first
         // chunk's here, the next one's during a chunk's 3x3x3 phase, which touches none of these.
-        // A chunk that takes over ncar >= 0 strong voxels of its two bottom levels has no planes
-        // for them (plane i of the storage holds local level i + skip) and opens its hotspot list
-        // with the carried voxels and their scores.
-        auto prepare = [&](int c0, int c1, int ncar) {
+        // A chunk that takes over the strong voxels of its two bottom levels (skip = 2) has no
+        // planes for them: plane i of the storage holds local level i + skip.
+        auto prepare = [&](int c0, int c1, int skip) {
             const int l0 = c0 - 1, l1 = c1;
             const int nlev = l1 - l0 + 1;
-            const int words = ((nlev - (ncar >= 0 ? 2 : 0)) * plane_u16(sKt[l1])) >> 1;   // whole uint4s
+            const int words = ((nlev - skip) * plane_u16(sKt[l1])) >> 1;   // whole uint4s
             uint4* a4 = reinterpret_cast<uint4*>(sA);
             const uint4 z = make_uint4(0u, 0u, 0u, 0u);
             for (int i = tid; i < (words >> 2); i += NT) a4[i] = z;
             for (int i = (words & ~3) + tid; i < words; i += NT) sA[i] = 0u;
-            for (int i = tid; i < ncar; i += NT) {
-                sHot[i] = sCarryId[i];
-                sHS[i] = sCarryS[i];
-            }
             for (int i = tid; i < nlev * NWW; i += NT) {
                 const int li = i / NWW, j = i - li * NWW;
                 const int lg = l0 + li, K = sKt[lg];
@@ -286,11 +281,11 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 sWpE[li][j] = wl[0] | (wl[1] << 16);
                 sWpO[li][j] = wl[1] | (wl[2] << 16);
             }
-            if (tid == 0) sNh = ncar > 0 ? static_cast<uint32_t>(ncar) : 0u;
+            if (tid == 0) sNh = 0;
         };
-        int carry_n = -1;                                     // voxels carried into the next chunk
+        bool carry = false;                                   // strong voxels handed to the next chunk
         int rc0 = 1, rc1 = chunk_end(1, 0);                   // the chunk's peak levels [rc0, rc1)
-        prepare(rc0, rc1, -1);
+        prepare(rc0, rc1, 0);
         __syncthreads();
         stamp(PH_SETUP);
         if (PHASES) ++ph_tiles;
@@ -298,9 +293,17 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         for (bool first_chunk = true;; first_chunk = false) {
             // local levels below `skip` were scored by the previous chunk, which handed over
             // their ncar strong voxels (the scores of a level do not depend on the chunk: its
-            // window lies inside every chunk's accumulator region that holds the level)
-            const int skip = carry_n >= 0 ? 2 : 0, ncar = max(carry_n, 0);
-            carry_n = -1;
+            // window lies inside every chunk's accumulator region that holds the level).  They
+            // join the hotspot list with their scores while the votes run.
+            const int skip = carry ? 2 : 0, ncar = carry ? static_cast<int>(sGat) : 0;
+            carry = false;
+            for (int i = tid; i < ncar; i += NT) {
+                const uint32_t h = atomicAdd(&sNh, 1u);
+                if (h < static_cast<uint32_t>(HCAP)) {
+                    sHot[h] = sCarryId[i];
+                    sHS[h] = sCarryS[i];
+                }
+            }
             const int l0 = rc0 - 1, l1 = rc1;                // accumulator level indices, inclusive
             const int nlev = l1 - l0 + 1;
             const int Kc = sKt[l1];                           // widest window of the chunk
@@ -311,10 +314,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
             const int plane = AWP * AH;                       // u16 per level, multiple of 8
             // the score region (tile + 1 px) in histogram coordinates
             const int hu0 = sx0 - ax0, hw = sx1 - sx0, hv0 = sy0 - ay0, hh = sy1 - sy0;
-            if (tid == 0) {                                   // last read by the previous 3x3x3 phase
-                sNs = 0;
-                sGat = 0;                                     // and before the previous prepare
-            }
+            if (tid == 0) sNs = 0;                            // last read by the previous 3x3x3 phase
             if (tid < NLEV_MAX) sLevN[tid] = 0u;
             // ---- votes of the staged ridges.  Only ridges with a sign that can reach the tile
             // are staged.  They are staged once per tile when they fit (ACAP); otherwise the
@@ -508,6 +508,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 stamp(PH_VOTE);
                 if (pc + 1 >= sNPieces) break;
             }
+            if (tid == 0) sGat = 0;                           // read before the votes' barrier
 
             const int SHh = sy1 - sy0;
 
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                                 sCarryS[k] = sStrongS[j];
                             }
                         }
-                        carry_n = 0;                           // counted after the next barrier
+                        carry = true;                          // counted after the next barrier
                     }
                     if (windows) continue;                     // round 1 takes the first window
                 }
@@ -834,15 +835,11 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 __syncthreads();
                 stamp(PH_PEAK);
             }
-            if (carry_n >= 0) {
-                __syncthreads();                              // the carried list is complete
-                carry_n = static_cast<int>(sGat);
-            }
             const bool last = rc1 > L - 2;
             if (!last) {
                 rc0 = rc1;
-                rc1 = chunk_end(rc0, carry_n >= 0 ? 2 : 0);
-                prepare(rc0, rc1, carry_n);
+                rc1 = chunk_end(rc0, carry ? 2 : 0);
+                prepare(rc0, rc1, carry ? 2 : 0);
             }
             __syncthreads();
             stamp(PH_PREP);
@@ -932,6 +929,7 @@ __global__ __launch_bounds__(CNT_) void k_tile_cost(TileCostArgs a) {
     for (int i = tid; i < CWIN; i += CNT_) sCnt[i] = 0u;
     __syncthreads();
     const uint32_t total = sPre[COST_CHUNK];
+    const uint32_t mT = 0xffffffffu / static_cast<uint32_t>(T) + 1u;   // floor(v / T) = mulhi(v, mT), v < 2^16
     for (uint32_t task = tid; task < 2 * total; task += CNT_) {
         const uint32_t k = task >> 1;
         const int sg = static_cast<int>(task & 1u);
@@ -946,7 +944,8 @@ __global__ __launch_bounds__(CNT_) void k_tile_cost(TileCostArgs a) {
             const int r = a.rbase + a.rstep * l;
             const int vx = x + ((r * sqx + rnd) >> 14), vy = y + ((r * sqy + rnd) >> 14);
             if (vx < 0 || vx >= W || vy < 0 || vy >= H) continue;
-            const int tx = vx / T, ty = vy / T;
+            const int tx = static_cast<int>(div_mulhi(static_cast<uint32_t>(vx), T, mT));
+            const int ty = static_cast<int>(div_mulhi(static_cast<uint32_t>(vy), T, mT));
             if (in_lds && tx >= wx0 && tx <= wx1 && ty >= wy0 && ty <= wy1)
                 atomicAdd(&sCnt[(ty - wy0) * nwx + (tx - wx0)], 1u);
             else
