@@ -609,13 +609,17 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                 }
                 const int nh = static_cast<int>(min(sNh, static_cast<uint32_t>(HCAP)));
                 // one task per hotspot, 8-column band of its window (16-byte aligned in the row)
-                // and half of the window's row distances: the band's eight horizontal weights
-                // stay in registers while the task walks its rows with one 16-byte load each
-                const int ntk = 2 * nbm;
+                // and part of the window's row distances: the band's eight horizontal weights
+                // stay in registers while the task walks its rows with one 16-byte load each.
+                // The distances go in two parts, or in four or eight while the tasks still fit
+                // one pass of the workgroup (a short list then waits on shorter row walks).
+                int psh = 1;
+                while (psh < 3 && (nh * nbm << (psh + 1)) <= NT) ++psh;
+                const int ntk = nbm << psh;
                 const uint32_t mB = 0xffffffffu / static_cast<uint32_t>(ntk) + 1u;
                 for (int task = tid; task < nh * ntk; task += NT) {
                     const int h = static_cast<int>(div_mulhi(static_cast<uint32_t>(task), ntk, mB));
-                    const int sub = task - h * ntk, bi = sub >> 1, half = sub & 1;
+                    const int sub = task - h * ntk, bi = sub >> psh, part = sub & ((1 << psh) - 1);
                     const uint32_t e = sHot[h];
                     const int li = e >> 16, sidx = e & 0xffff;
                     if (li < skip) continue;                       // carried with its score
@@ -630,13 +634,14 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     const int o = ax0 + c0 - vx + WC;               // WC - K - 7 >= 1, o + 7 < 2 WC
                     const uint32_t* wp = (o & 1) ? &sWpO[li][o >> 1] : &sWpE[li][o >> 1];
                     const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
-                    // rows vy - d and vy + d share the weight W(d): the task takes d = 0 .. K/2
-                    // (half 0) or K/2 + 1 .. K (half 1), rows clipped to the region, and weights
-                    // the sum of a pair's two bands once.  A counter takes at most one vote per
+                    // rows vy - d and vy + d share the weight W(d): part p of the 2^psh takes
+                    // d = floor(p (K + 1) / 2^psh) .. floor((p + 1) (K + 1) / 2^psh) - 1 (the
+                    // parts cover 0 .. K once; some are empty for small K), rows clipped to the
+                    // region, and weights the sum of a pair's two bands once.  A counter takes at most one vote per
                     // lattice offset the rounded r X_- can reach (1016 at r = 127, the largest
                     // level), so two 8-tap bands of weights <= 2^15 stay below 2^31 and the
                     // 32-bit sum is exact.
-                    const int dlo = half ? (K >> 1) + 1 : 0, dhi = half ? K : (K >> 1);
+                    const int dlo = (part * (K + 1)) >> psh, dhi = (((part + 1) * (K + 1)) >> psh) - 1;
                     const int up_max = vy - ay0, dn_max = ay1 - 1 - vy;   // farthest rows in the region
                     const int rstep = AWP >> 3;
                     const uint4* rowc = reinterpret_cast<const uint4*>(sA) + (((li - skip) * plane + (vy - ay0) * AWP + c0) >> 3);
