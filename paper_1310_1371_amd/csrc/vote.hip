@@ -435,19 +435,22 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                     stamp(PH_SORT);
                 }
                 // votes: each staged (ridge, sign) item over its level range clipped to this
-                // chunk, split between two lanes (half of the levels each), which spreads the
-                // loop over more waves; the region test below rejects the votes that land in
-                // the tile's widest region but outside this chunk's
-                const int nact = static_cast<int>(sNact);
-                for (int k = tid; k < 2 * nact; k += NT) {
-                    const int it = sOrd[k >> 1];
+                // chunk, split between two lanes, or four or eight while the items that start
+                // by this chunk's top level (the sorted prefix up to the end of that key's
+                // bucket) still fit one pass of the workgroup; the region test below rejects
+                // the votes that land in the tile's widest region but outside this chunk's
+                const int nc = static_cast<int>(min(sKey[l1], sNact));
+                int vsh = 1;
+                while (vsh < 3 && (nc << (vsh + 1)) <= NT) ++vsh;
+                for (int k = tid; k < (nc << vsh); k += NT) {
+                    const int it = sOrd[k >> vsh];
                     const int jr = it >> 1, sg = it & 1;
                     const uint32_t rr = sRidR[jr] >> (16 * sg);
-                    const int la_raw = static_cast<int>(rr & 0xffu);
-                    if (la_raw > l1) break;                       // the rest start later still
-                    const int la0 = max(la_raw, l0 + skip), lb0 = min(static_cast<int>((rr >> 8) & 0xffu), l1);
-                    const int mid = (la0 + lb0) >> 1;
-                    const int la = (k & 1) ? mid + 1 : la0, lb = (k & 1) ? lb0 : mid;
+                    const int la0 = max(static_cast<int>(rr & 0xffu), l0 + skip);
+                    const int n = min(static_cast<int>((rr >> 8) & 0xffu), l1) - la0 + 1;
+                    if (n <= 0) continue;
+                    const int part = k & ((1 << vsh) - 1);
+                    const int la = la0 + ((part * n) >> vsh), lb = la0 + (((part + 1) * n) >> vsh) - 1;
                     if (la > lb) continue;
                     const uint32_t xy = sRidXY[jr], q = sRidQ[jr];
                     const int x = (xy & 0xffffu) - ax0, y = (xy >> 16) - ay0;
