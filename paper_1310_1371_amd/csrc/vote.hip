@@ -16,7 +16,7 @@
 //   3. lists the hotspots (A > T_int) of the tile + 1 px as they arise: the atomic returns
 //      the counter's old value, and the vote that lifts it past T_int lists the voxel;
 //   4. evaluates the integer score S_int = sum W(|dx|) W(|dy|) A of each hotspot with 15-bit
-//      weight factors, in tasks of one 8-column band of the window and half its rows, and
+//      weight factors, in tasks of one 8-column band of the window and part of its rows, and
 //      keeps the scores above the level's integer threshold in a "strong" list;
 //   5. tests each strong voxel of the peak levels against the strong voxels of its 3x3x3 box
 //      (scores at different levels compare as S_int / r, exactly, by cross-multiplication; a
