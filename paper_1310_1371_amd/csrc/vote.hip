@@ -802,8 +802,9 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
                         if (candidate(j, li, lm, sxr, syr) && !sBad[j]) emit(j, lm, sxr, syr);
                     }
                 } else {
-                    // a short list: G lanes per strong voxel, each comparing a slice of the list
-                    const int gs = ns > 32 ? 3 : 0;
+                    // a short list: G lanes per strong voxel, each comparing a slice of about two
+                    // entries of the list (one lane when the list holds at most four)
+                    const int gs = ns <= 4 ? 0 : min(4, 31 - __builtin_clz(static_cast<unsigned>(ns - 1)));
                     const int G = 1 << gs;
                     for (int task = tid; task < (ns << gs); task += NT) {
                         const int j = task >> gs, g = task & (G - 1);
