@@ -277,6 +277,46 @@ def test_crowded_tile_windows_exact(det, f, tint):
             assert abs(float(kr[k][fld]) - float(kg[k][fld])) <= 0.05
 
 
+def _dense_rings(tint):
+    """40 rings of radius 6-28 on a 200^2 frame (radii 5-30): about 3600 ridges."""
+    rng = np.random.default_rng(5)
+    k = 40
+    cx, cy, R = rng.uniform(20, 180, k), rng.uniform(20, 180, k), rng.uniform(6, 28, k)
+    img = synth.render(200, 200, np.full((200, 200), 0.2), cx, cy, R, np.full(k, 1.5), np.ones(k))
+    p = dict(O.DEFAULTS, **dict(synth.PARAMS_C1, r_min=5, r_max=30, vote_threshold=tint))
+    return img.astype(np.float32), p
+
+
+def test_per_level_hotspots_with_handed_over_levels(det):
+    """With T_int = 0 a tile lists more hotspots in a level chunk after its first than the list
+    holds (over 1792 at levels 20-27), so that chunk lists its hotspots level by level, while
+    the strong voxels stay few (no window): the chunk takes its two bottom levels from the
+    strong voxels the previous chunk handed over, also in the level-by-level listing.  Rings
+    equal the oracle's from the same ridges."""
+    say("[per-level hotspots after a hand-over] 200^2, 40 rings, T_int = 0")
+    img, p = _dense_rings(0)
+    H, W = img.shape
+    xs, ys, qx, qy, _ = O.ridges(img, p)
+    ref, A_ref, S_ref = O.detect_from_ridges(xs, ys, qx, qy, W, H, p, return_volumes=True)
+    lbase = p["r_min"] - 1
+    thr = np.array([O.score_threshold(lbase + i, p) for i in range(S_ref.shape[0])])
+    strong = S_ref > thr[:, None, None]
+    region = [(max(y - 1, 0), y + 41, max(x - 1, 0), x + 41) for y in range(0, H, 40) for x in range(0, W, 40)]
+    hot_late = max(int((A_ref[20:, y0:y1, x0:x1] > 0).sum()) for y0, y1, x0, x1 in region)
+    most_strong = max(int(strong[:, y0:y1, x0:x1].sum()) for y0, y1, x0, x1 in region)
+    say(f"  most hotspots of a tile at levels 20-27: {hot_late}; most strong voxels of a tile: {most_strong}")
+    assert hot_late > 1792 and most_strong < 512    # the case does exercise that path
+    xy = np.stack([xs, ys], 1).astype(np.int32)
+    q = np.stack([qx, qy], 1).astype(np.int16)
+    got = det.detect_from_ridges(xy, q, W, H, p)
+    assert [tuple(int(v) for v in (r["a"], r["b"], r["r_bin"])) for r in ref] == \
+           [tuple(int(v) for v in (r["a"], r["b"], r["r_bin"])) for r in got]
+    np.testing.assert_array_equal(ref["n_fit"], got["n_fit"])
+    np.testing.assert_array_equal(ref["fit_ok"], got["fit_ok"])
+    for fld in ("cx", "cy", "r", "score"):
+        np.testing.assert_allclose(got[fld], ref[fld], rtol=2e-7, atol=1e-9)
+
+
 def test_crowded_tile_overflow_reported(det):
     """With f = 0.1 and T_int = 1 a window of one peak level (three levels) holds more
     above-threshold voxels than the list: RD_E_OVERFLOW, not a partial answer."""
