@@ -80,11 +80,22 @@ def parse():
     return ap.parse_args()
 
 
+def list_schedule(durations, workers):
+    """Makespan when each of `workers` takes the next duration of the list as it becomes free."""
+    import heapq
+    free = [0.0] * workers
+    for d in durations:
+        heapq.heapreplace(free, free[0] + float(d))
+    return max(free)
+
+
 def vote_phases():
     """Where the vote kernel's time goes: shader clocks per phase (summed over workgroups,
     shares of their summed lifetimes, clocks per tile) on the headline c2 frame and on the first
-    2048^2 stream frame, from the library's phase-timed instance of the kernel; best of 3
-    calls by lifetime."""
+    2048^2 stream frame, from the library's phase-timed instance of the kernel (best of 3
+    calls by lifetime), and the tiles' own durations from one more such call, with the
+    makespans their queue order and a longest-first order would give."""
+    import numpy as np
     import torch
 
     from paper_1310_1371_amd import synth
@@ -102,7 +113,16 @@ def vote_phases():
         det.detect(img, p)
         best = min((det.profile_vote_phases(img, p) for _ in range(3)), key=lambda r: r["lifetime_sum"])
         life = best["lifetime_sum"]
-        out[name] = {"tiles": best["tiles"],
+        rec = det.profile_vote_tiles(img, p)
+        dur = (rec[:, 3] - rec[:, 2]).astype(float)
+        by_queue = dur[np.argsort(rec[:, 1])]
+        out_tiles = {"mean_clocks": float(dur.mean()), "max_clocks": float(dur.max()),
+                     "median_clocks": float(np.median(dur)), "mean_work_per_cu": float(dur.sum() / cus),
+                     # each workgroup takes the next tile when it is free: the makespan of the
+                     # launch's queue order with the measured tile times, and of longest first
+                     "queue_order_makespan": list_schedule(by_queue, cus),
+                     "longest_first_makespan": list_schedule(np.sort(dur)[::-1], cus)}
+        out[name] = {"tiles": best["tiles"], "per_tile": out_tiles,
                      "clocks_per_tile": {k: v / best["tiles"] for k, v in best["phases"].items()},
                      "share_of_lifetimes": {k: v / life for k, v in best["phases"].items()},
                      "mean_tile_clocks": sum(best["phases"].values()) / best["tiles"],

@@ -238,6 +238,18 @@ rd_status rd_measure_lds_atomics(int32_t device, int32_t with_return, double* at
 #define RD_VOTE_PHASE_WORDS 12
 rd_status rd_profile_vote_phases(rd_handle h, const rd_frame* frame, const rd_params* params, uint64_t* clocks);
 
+/* Measurement only: the same profiled rd_detect, recording each vote tile of the frame.
+ * records (host, 4 x capacity words) receive for vote tile t (row-major over the frame's
+ * T x T tiles) at records[4 t .. 4 t + 3]: the workgroup that ran it, its position in the
+ * launch's queue, the shader clock when the workgroup took it and the clock when that
+ * workgroup took its next tile or ended.  Workgroups on different XCDs read different clocks,
+ * so only a tile's end minus its start is meaningful.  *n_tiles receives the frame's vote
+ * tiles; RD_E_TRUNCATED (nothing written) when they exceed capacity.  Same validation as
+ * rd_detect; RD_E_OVERFLOW as rd_detect. */
+#define RD_VOTE_TILE_WORDS 4
+rd_status rd_profile_vote_tiles(rd_handle h, const rd_frame* frame, const rd_params* params, uint64_t* records,
+                                int32_t capacity, int32_t* n_tiles);
+
 /* ---- stage entry points (parity checks; same kernels as rd_detect) ------------------- */
 
 /* Step 1 only: k_- (float, H x W, row-major, device pointer) and the direction code of

@@ -321,7 +321,10 @@ rd_status enqueue(rd_ctx* h, const rd_params& p, int nframes, int dtype, int rg,
         RD_HIP(launch_tile_cost(ta, h->n_chunks, h->stream));
         va.tile_order = h->d_torder;
     }
-    if (h->phase_on) va.phase_clocks = h->d_phase;
+    if (h->phase_on) {
+        va.phase_clocks = h->d_phase;
+        va.tile_clocks = h->trec_on ? h->d_trec : nullptr;
+    }
     RD_HIP(launch_vote(va, h->tabs.lds, false, h->cus, h->stream));
     RD_TRY(mark(h, 2));
     RD_HIP(launch_fit(fit_args(h, p, nframes, rings, counts_out), FIT_GRID, h->stream));
@@ -680,6 +683,7 @@ void rd_destroy(rd_handle h) {
     (void)hipFree(h->d_eoff);
     (void)hipFree(h->d_tcost);
     (void)hipFree(h->d_phase);
+    (void)hipFree(h->d_trec);
     (void)hipFree(h->d_torder);
     for (hipEvent_t& e : h->ev)
         if (e) (void)hipEventDestroy(e);
@@ -733,6 +737,32 @@ rd_status rd_profile_vote_phases(rd_handle h, const rd_frame* frame, const rd_pa
     RD_HIP(hipMemcpyAsync(out, h->d_phase, sizeof(out), hipMemcpyDeviceToHost, h->stream));
     RD_HIP(hipStreamSynchronize(h->stream));
     for (int i = 0; i < PH_COUNT + 4; ++i) clocks[i] = out[i];
+    return RD_OK;
+}
+
+rd_status rd_profile_vote_tiles(rd_handle h, const rd_frame* frame, const rd_params* params, uint64_t* records,
+                                int32_t capacity, int32_t* n_tiles) {
+    if (!h || !n_tiles || capacity < 0 || (capacity > 0 && !records)) return RD_E_INVALID;
+    *n_tiles = 0;
+    RD_TRY(rd_validate_params(params));
+    RD_TRY(check_frame(h, frame));
+    const int tv = vote_tiles(frame->width, frame->height, vote_tile_for(params->measure));
+    *n_tiles = tv;
+    if (tv > capacity) return RD_E_TRUNCATED;
+    RD_HIP(hipSetDevice(h->device));
+    if (h->trec_cap < tv) {
+        (void)hipFree(h->d_trec);
+        h->d_trec = nullptr;
+        h->trec_cap = 0;
+        RD_HIP(hipMalloc(reinterpret_cast<void**>(&h->d_trec), static_cast<size_t>(tv) * RD_VOTE_TILE_WORDS * 8));
+        h->trec_cap = tv;
+    }
+    uint64_t clocks[RD_VOTE_PHASE_WORDS];
+    h->trec_on = true;
+    const rd_status st = rd_profile_vote_phases(h, frame, params, clocks);
+    h->trec_on = false;
+    if (st != RD_OK) return st;
+    RD_HIP(hipMemcpy(records, h->d_trec, static_cast<size_t>(tv) * RD_VOTE_TILE_WORDS * 8, hipMemcpyDeviceToHost));
     return RD_OK;
 }
 

@@ -105,6 +105,9 @@ struct rd_ctx {
     uint32_t* d_tcost = nullptr;
     unsigned long long* d_phase = nullptr;   // rd_profile_vote_phases: the clocks (allocated on first use)
     bool phase_on = false;
+    unsigned long long* d_trec = nullptr;     // rd_profile_vote_tiles: 4 words per vote tile
+    int64_t trec_cap = 0;                     // tiles d_trec holds
+    bool trec_on = false;
     int vtile = rd::VOTE_TILE_RIDGE;        // vote tile of the parameters the tables were set up for
     uint32_t* d_torder = nullptr;
     int n_chunks = 0;                   // COST_CHUNK-bin chunks of the current launch's frames

@@ -101,6 +101,8 @@ struct VoteArgs {
     uint64_t* score_dump;
     const uint32_t* tile_order;  // [total_vtiles] the queue's tiles, estimated costliest first (may be null)
     unsigned long long* phase_clocks;  // profiling instance: [PH_COUNT + 4] (null: the plain kernel)
+    unsigned long long* tile_clocks;   // profiling instance, may be null: per tile [workgroup,
+                                       // queue position, clock at start, clock at end]
     int32_t tile;                // T of the T x T vote tiles (VOTE_TILE_RIDGE or VOTE_TILE_EDGE)
 };
 

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
     // phase clocks (the profiling instance only): thread 0 reads the shader clock after the
     // barrier that ends each phase, so each span is the workgroup's
     unsigned long long ph_acc[PH_COUNT] = {}, ph_last = 0, ph_start = 0;
-    int ph_tiles = 0;
+    int ph_tiles = 0, ph_tile = -1;
     if (PHASES && tid == 0) ph_start = ph_last = __builtin_readcyclecounter();
     auto stamp = [&](int ph) {
         if (PHASES && tid == 0) {
@@ -183,7 +183,18 @@ __global__ __launch_bounds__(NT) void k_vote(VoteArgs a) {
         // tiles are taken from a queue: their cost varies with the number of hotspots
         if (tid == 0) {
             int tq = static_cast<int>(atomicAdd(a.tile_counter, 1u));
+            const int qpos = tq;
             if (a.tile_order && tq < a.total_vtiles) tq = static_cast<int>(a.tile_order[tq]);   // costliest first
+            if (PHASES && a.tile_clocks) {         // the previous tile's end, this one's start
+                const unsigned long long now = __builtin_readcyclecounter();
+                if (ph_tile >= 0) a.tile_clocks[4 * ph_tile + 3] = now;
+                ph_tile = tq < a.total_vtiles ? tq : -1;
+                if (ph_tile >= 0) {
+                    a.tile_clocks[4 * tq] = blockIdx.x;
+                    a.tile_clocks[4 * tq + 1] = static_cast<unsigned long long>(qpos);
+                    a.tile_clocks[4 * tq + 2] = now;
+                }
+            }
             int fq = 0;                             // last frame whose first vote tile is <= tq
             for (int hi = a.nframes; hi - fq > 1;) {
                 const int mid = (fq + hi) >> 1;

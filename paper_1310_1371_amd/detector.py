@@ -238,6 +238,21 @@ class Detector:
         return {"phases": dict(zip(self.PHASES, [int(v) for v in c[:n]])), "lifetime_sum": int(c[n]),
                 "tiles": int(c[n + 1]), "lifetime_max": int(c[n + 2]), "lifetime_min": int(c[n + 3])}
 
+    def profile_vote_tiles(self, frame, params: dict):
+        """One detection with the phase-timed vote kernel, per vote tile: an int64 [n, 4] array of
+        (workgroup, queue position, clock at start, clock at end); only end - start compares
+        across workgroups."""
+        import numpy as np
+        fr = _frame_struct(frame)
+        p = N.make_params(params)
+        n = ctypes.c_int32(0)
+        self._lib.rd_profile_vote_tiles(self._h, ctypes.byref(fr), ctypes.byref(p), None, 0, ctypes.byref(n))
+        rec = np.zeros((max(n.value, 1), 4), dtype=np.uint64)
+        N.check(self._lib.rd_profile_vote_tiles(self._h, ctypes.byref(fr), ctypes.byref(p),
+                                                rec.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)),
+                "rd_profile_vote_tiles")
+        return rec[:n.value].astype(np.int64)
+
     def curvature(self, frame, params: dict):
         """k_- (float32 [H, W]) and direction codes (int16 [H, W, 2]) as CUDA tensors."""
         fr = _frame_struct(frame)

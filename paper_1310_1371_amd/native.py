@@ -93,6 +93,7 @@ SIGNATURES = {
     "rd_fit_loss": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp]),
     "rd_fit_loss_backward": (ctypes.c_int, [_vp, _P(RdFrame), _vp, _vp, _i64, ctypes.c_double, _vp, _vp, _vp]),
     "rd_profile_vote_phases": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp]),
+    "rd_profile_vote_tiles": (ctypes.c_int, [_vp, _P(RdFrame), _P(RdParams), _vp, ctypes.c_int32, _P(ctypes.c_int32)]),
     "rd_soft_ridges_batch": (ctypes.c_int, [_vp, _P(RdFrame), _i32, _P(RdParams), _vp, _vp, _i64, _vp]),
     "rd_soft_forward_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _P(RdParams), _vp]),
     "rd_soft_backward_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _P(RdParams), _vp, _vp,

@@ -215,3 +215,23 @@ def test_stats_counts(bdet):
     assert st["peaks"] == len(rings)
     assert abs(st["ridges"] - len(xs)) <= max(1, 1e-4 * len(xs))
     assert st["votes"] > 0 and st["hotspots"] > 0 and st["strong"] >= st["peaks"]
+
+
+def test_vote_profiles(bdet):
+    """The profiling instance of the vote kernel: the same rings as the plain call, phase clocks
+    over every tile, and one record per vote tile (each queue position once, the ridge tiles
+    of 40 px, every workgroup below the CU count, end after start)."""
+    say("[vote profiles]")
+    f = synth.config2(seed=21, W=300, H=170, n_rings=12)
+    img = torch.from_numpy(f.image).cuda()
+    ref = bdet.detect(img, f.params)
+    ph = bdet.profile_vote_phases(img, f.params)
+    tiles = ((300 + 39) // 40) * ((170 + 39) // 40)
+    assert ph["tiles"] == tiles and all(v > 0 for v in ph["phases"].values())
+    assert ph["lifetime_min"] <= ph["lifetime_max"]
+    rec = bdet.profile_vote_tiles(img, f.params)
+    assert rec.shape == (tiles, 4)
+    assert sorted(rec[:, 1].tolist()) == list(range(tiles))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert (rec[:, 0] >= 0).all() and (rec[:, 0] < cus).all() and (rec[:, 3] > rec[:, 2]).all()
+    assert bdet.detect(img, f.params).tobytes() == ref.tobytes()
