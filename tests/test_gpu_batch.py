@@ -235,3 +235,12 @@ def test_vote_profiles(bdet):
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert (rec[:, 0] >= 0).all() and (rec[:, 0] < cus).all() and (rec[:, 3] > rec[:, 2]).all()
     assert bdet.detect(img, f.params).tobytes() == ref.tobytes()
+    # a record buffer short of the frame's tiles: RD_E_TRUNCATED with the count, nothing written
+    import ctypes
+    from paper_1310_1371_amd import native as N
+    from paper_1310_1371_amd.detector import _frame_struct
+    buf = np.full(4 * (tiles - 1), 7, dtype=np.uint64)
+    n = ctypes.c_int32(0)
+    st = N.lib().rd_profile_vote_tiles(bdet._h, ctypes.byref(_frame_struct(img)), ctypes.byref(N.make_params(f.params)),
+                                       buf.ctypes.data_as(ctypes.c_void_p), tiles - 1, ctypes.byref(n))
+    assert st == N.RD_E_TRUNCATED and n.value == tiles and (buf == 7).all()
